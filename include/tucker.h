@@ -1,0 +1,202 @@
+/*
+ * tucker.h -- C ABI of the MI355X dense Tucker / HOOI library (libtucker.so).
+ *
+ * The library computes the TTM component of HOOI (Chakaravarthy et al.,
+ * "On Optimizing Distributed Tucker Decomposition for Dense Tensors",
+ * arXiv 1707.05594) on one AMD Instinct MI355X (gfx950):
+ *
+ *   for every mode n:  Y_n = T x_{m != n} F_m^T  through a TTM-tree
+ *                      (Sec. 3.1 definition; optimal tree by the dynamic
+ *                      program of Sec. 3.3),
+ *                      F~_n = leading K_n left singular vectors of Y_(n),
+ *                      taken from the Gram matrix Y_(n) Y_(n)^T and an FP64
+ *                      eigensolver (Sec. 5, Gram + EVD),
+ *   then the new core G~ = T x_1 F~_1^T ... x_N F~_N^T and the error
+ *   (Fig. 2, "HOOI Procedure"; Sec. 2.2 error).
+ *
+ * Conventions
+ *   - Modes are 0-based (the paper numbers them from 1).
+ *   - Tensors are dense, row-major, last mode fastest.  An N-mode tensor with
+ *     lengths L_0..L_{N-1} is a contiguous array of prod(L) elements.
+ *   - Factor matrices F_n are L_n x K_n, row-major, FP64 on the host side.
+ *   - "Device pointer" means memory from hipMalloc (or a torch CUDA tensor) on
+ *     the current HIP device; "host pointer" means ordinary process memory.
+ *   - Costs are counted in multiply-adds: the paper's FLOP count of a TTM,
+ *     K_n |In(u)| (Sec. 3.1), is one multiply-add per term.
+ *   - Every function returns TK_OK (0) or a negative error code; the text of
+ *     the last error on the calling thread is returned by tk_last_error().
+ *     On error no output argument is written unless stated otherwise.
+ *   - All device work is enqueued on the stream given to hooi_init (or to the
+ *     kernel-level entry points); functions that return host data
+ *     synchronise that stream before returning.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define TK_OK 0
+#define TK_EINVAL (-1)        /* bad argument: sizes, null pointer, mismatch   */
+#define TK_ENOMEM (-2)        /* device or host allocation failed              */
+#define TK_EDEVICE (-3)       /* a HIP runtime call or kernel launch failed    */
+#define TK_ENUMERIC (-4)      /* NaN/Inf met, or the eigensolver did not converge */
+#define TK_EUNSUPPORTED (-5)  /* unsupported storage/compute combination       */
+
+#define TK_MAX_MODES 12       /* the planner is O(4^N) (Sec. 3.3)              */
+
+/* storage type of T (and of kernel-level operands) */
+#define TK_F64 0
+#define TK_F32 1
+#define TK_BF16 2
+
+/* arithmetic of the TTM and Gram kernels.  The eigensolver, the factor
+ * orthonormalisation, norms and the error are FP64 in every mode. */
+#define TK_C_FP64 0   /* FP64 operands, FP64 accumulation (T stored F64)          */
+#define TK_C_FP32 1   /* FP32 operands on FP32 MFMA, FP32 accumulation            */
+#define TK_C_BF16 2   /* BF16 operands on BF16 MFMA, FP32 accumulation            */
+#define TK_C_BF16X3 3 /* split BF16: a*b ~ ah*bh + ah*bl + al*bh, FP32 accumulation */
+
+/* tree kinds (Sec. 3.2 prior schemes, Sec. 3.3 optimal tree) */
+#define TK_TREE_DP 0        /* minimum multiply-add tree, dynamic program         */
+#define TK_TREE_CHAIN 1     /* N independent chains, ascending modes (naive)      */
+#define TK_TREE_CHAIN_K 2   /* chains in increasing-K_n mode order                */
+#define TK_TREE_CHAIN_H 3   /* chains in increasing h_n = K_n/L_n mode order      */
+#define TK_TREE_BALANCED 4  /* divide-and-conquer tree, input mode order          */
+
+typedef struct tk_plan tk_plan; /* host-only, owned by the caller (tk_plan_free) */
+typedef struct tk_ctx tk_ctx;   /* device state, owned by the caller (hooi_free) */
+
+/* One node of a TTM-tree, in depth-first execution order (parents first). */
+typedef struct {
+  int32_t parent;    /* index of the parent node; -1 when the parent is the root T */
+  int32_t mode;      /* TTM mode of an internal node, or the factor mode of a leaf */
+  int32_t is_leaf;   /* 1 for a leaf F~_n, 0 for an internal (TTM) node           */
+  int32_t depth;     /* 0 for children of the root                                */
+  uint64_t in_card;  /* |In(u)|: elements of the tensor the node reads            */
+  uint64_t out_card; /* |Out(u)| = (K_n/L_n)|In(u)| for internal nodes, 0 for leaves */
+  uint64_t macs;     /* K_n |In(u)| for internal nodes, 0 for leaves (Sec. 3.1)   */
+  uint32_t pre_mask; /* bit j set: mode j already multiplied in In(u)             */
+  uint32_t pad_;
+} tk_node;
+
+/* ---- planning (host only; Sec. 3.1 cost, Sec. 3.2 heuristics, Sec. 3.3 DP) -- */
+
+/* Build a TTM-tree plan for lengths L[0..N-1] and core lengths K[0..N-1].
+ * kind: TK_TREE_*.  topk >= 1: for TK_TREE_DP the plan keeps the topk cheapest
+ * distinct trees (rank 0 = the optimum with the documented tie rule); other
+ * kinds hold one tree.
+ * Requires 2 <= N <= TK_MAX_MODES, 1 <= K_n <= L_n, K_n <= prod_{m != n} K_m
+ * (otherwise Y_(n) cannot have rank K_n), prod(L) < 2^62.  TK_EINVAL otherwise.
+ * *out receives a new plan owned by the caller. */
+int ttm_tree_plan(int N, const int64_t* L, const int64_t* K, int kind, int topk,
+                  tk_plan** out);
+int tk_plan_count(const tk_plan* plan, int* count);          /* trees held */
+int tk_plan_cost(const tk_plan* plan, int rank, uint64_t* macs);
+/* Canonical text: leaf "F<n>", node "m<n>(children)", root "T(children)",
+ * children sorted as strings.  Writes at most cap bytes including the NUL;
+ * TK_EINVAL if cap is too small. */
+int tk_plan_string(const tk_plan* plan, int rank, char* buf, size_t cap);
+/* Copies up to cap nodes of tree `rank`; *n receives the node count. */
+int tk_plan_nodes(const tk_plan* plan, int rank, tk_node* out, int cap, int* n);
+/* DP instrumentation: table entries created and table lookups made. */
+int tk_plan_stats(const tk_plan* plan, uint64_t* entries, uint64_t* lookups);
+/* Largest per-path sum of live intermediate elements of tree `rank` (the DFS
+ * workspace bound of Sec. 3.1: at most depth-many intermediates alive). */
+int tk_plan_workspace(const tk_plan* plan, int rank, uint64_t* elements);
+/* Choose which held tree (rank) hooi_init executes; default rank 0. */
+int tk_plan_select(tk_plan* plan, int rank);
+void tk_plan_free(tk_plan* plan);
+
+/* ---- HOOI context ---------------------------------------------------------- */
+
+/* Create a context for HOOI on the tensor T.
+ *   T_dev: device pointer, row-major prod(L) elements of type tdtype; borrowed
+ *          (never written, never freed) and must outlive the context.
+ *   plan : tree to execute (NULL: the DP optimum).  Must have been built for
+ *          the same (N, L, K); its selected rank is copied, the plan may be freed.
+ *   compute: TK_C_*.  Supported: F64 storage with TK_C_FP64; F32 or BF16
+ *          storage with TK_C_FP32, TK_C_BF16, TK_C_BF16X3.
+ *   F0_host: NULL to start from HOSVD (F_n = leading K_n left singular vectors
+ *          of T_(n)), or host FP64 factors F_0..F_{N-1} concatenated, each
+ *          L_n x K_n row-major (checkpoint / resume).  Copied.
+ *   stream: hipStream_t (NULL = default stream) used for all device work.
+ * Allocates device workspace sized for the tree (TK_ENOMEM on failure). */
+int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, const void* T_dev,
+              const tk_plan* plan, int compute, const double* F0_host, void* stream,
+              tk_ctx** out);
+
+/* Run `iters` >= 1 HOOI invocations (Fig. 2, Jacobi form: every chain uses the
+ * factors from the start of the invocation).  rel_err: NULL or a host array of
+ * `iters` doubles that receives the relative error after each invocation,
+ * sqrt(max(||T||^2 - ||G~||^2, 0)) / ||T||.  Each invocation's new core is
+ * computed by folding it into the next tree pass (G = Y_n x_n F_n^T); the
+ * last one by a direct TTM chain.  Synchronises the stream before returning. */
+int hooi_iterate(tk_ctx* ctx, int iters, double* rel_err);
+
+/* Error of the current decomposition: *rel_err as above, *normT = ||T||_F,
+ * *normG = ||G||_F (any output may be NULL). */
+int tucker_error(tk_ctx* ctx, double* rel_err, double* normT, double* normG);
+
+/* Explicit residual ||T - G x_1 F_1 ... x_N F_N||_F / ||T||_F, accumulated in
+ * FP64 on the device without forming the recovered tensor. */
+int tucker_error_explicit(tk_ctx* ctx, double* rel_err);
+
+/* Copy out the current FP64 factor F_n (L_n x K_n row-major) / core
+ * (prod(K) row-major) to host memory. */
+int tk_get_factor(tk_ctx* ctx, int n, double* host);
+int tk_get_core(tk_ctx* ctx, double* host);
+/* Replace every factor by host FP64 factors (same layout as F0_host). */
+int tk_set_factors(tk_ctx* ctx, const double* host);
+
+/* One tree pass with the current factors, no factor update: fills the leaf
+ * tensors Y_n and Gram matrices S_n.  Then tk_get_leaf copies Y_n (row-major,
+ * lengths K_m for m != n and L_n at mode n, FP64-converted) and tk_get_gram
+ * copies S_n (L_n x L_n FP64) to host memory.  Test and inspection aids. */
+int tk_tree_pass(tk_ctx* ctx);
+int tk_get_leaf(tk_ctx* ctx, int n, double* host);
+int tk_get_gram(tk_ctx* ctx, int n, double* host);
+
+/* Per-node device time (ms, HIP events) of one tree pass with the current
+ * factors; ms_out has one entry per plan node (leaves: Gram time). */
+int tk_profile_tree(tk_ctx* ctx, float* ms_out, int cap, int* n);
+
+void hooi_free(tk_ctx* ctx);
+
+/* ---- kernel-level entry points (device pointers, enqueued on `stream`) ---- */
+
+/* TTM node (Sec. 2.1): with In viewed as [A, L, B] row-major,
+ *   Out[a, k, b] = sum_l F[l, k] * In[a, l, b],  0 <= k < K.
+ * in_dtype: TK_F64/TK_F32/TK_BF16 element type of In.  F: device, L x K
+ * row-major FP64 when compute == TK_C_FP64, else FP32.  Out: device,
+ * [A, K, B] of FP64 (compute FP64) or FP32.  K <= 512, L <= 65535.
+ * In and Out must not overlap. */
+int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
+           const void* F, int64_t K, void* out, void* stream);
+
+/* Gram (Sec. 5): with Y viewed as [A, L, B], S[i, j] = sum_{a,b} Y[a,i,b] Y[a,j,b],
+ * written as a full symmetric L x L FP64 matrix to device memory S.
+ * in_dtype: TK_F64 (FP64 arithmetic) or TK_F32 (FP32 products, FP64 sums of
+ * fixed-size column blocks, fixed order: deterministic).  L <= 1024. */
+int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
+            void* stream);
+
+/* Leading K eigenpairs of `count` symmetric L x L FP64 matrices (device,
+ * contiguous), eigenvalues descending, each eigenvector's largest-magnitude
+ * entry (lowest index on ties) made positive.  V0: NULL (cold start) or
+ * device L x K start blocks (warm start, e.g. the previous factors).
+ * F: device count x L x K row-major; evals: device count x K.  L <= 1024. */
+int tk_eig_leading(int count, int L, int K, const double* S, const double* V0, double* F,
+                   double* evals, void* stream);
+
+const char* tk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUCKER_H */

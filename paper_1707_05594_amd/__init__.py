@@ -1,0 +1,338 @@
+"""Python binding of libtucker (MI355X dense Tucker / HOOI, arXiv 1707.05594).
+
+Thin ctypes marshalling over the C ABI declared in include/tucker.h: every
+computation happens in the HIP library.  PyTorch is used only to hold device
+memory and to name the stream; tensors are passed by data pointer.
+
+The names follow the C ABI: ``ttm_tree_plan``, ``hooi_init``,
+``hooi_iterate``, ``tucker_error`` plus the inspection and kernel-level calls.
+If the library is missing this module raises at first use -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtucker.so")
+
+TK_OK, TK_EINVAL, TK_ENOMEM, TK_EDEVICE, TK_ENUMERIC, TK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+TK_F64, TK_F32, TK_BF16 = 0, 1, 2
+TK_C_FP64, TK_C_FP32, TK_C_BF16, TK_C_BF16X3 = 0, 1, 2, 3
+TREE_KINDS = {"dp": 0, "chain": 1, "chain_k": 2, "chain_h": 3, "balanced": 4}
+COMPUTE = {"fp64": TK_C_FP64, "fp32": TK_C_FP32, "bf16": TK_C_BF16, "bf16x3": TK_C_BF16X3}
+MAX_MODES = 12
+
+
+class TuckerError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libtucker error {code}: {msg}")
+        self.code = code
+
+
+class TkNode(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("is_leaf", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("in_card", ctypes.c_uint64), ("out_card", ctypes.c_uint64),
+                ("macs", ctypes.c_uint64), ("pre_mask", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+_SIGS = {
+    "ttm_tree_plan": ([ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(_vp)], ctypes.c_int),
+    "tk_plan_count": ([_vp, _ip], ctypes.c_int),
+    "tk_plan_cost": ([_vp, ctypes.c_int, _u64p], ctypes.c_int),
+    "tk_plan_string": ([_vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t], ctypes.c_int),
+    "tk_plan_nodes": ([_vp, ctypes.c_int, ctypes.POINTER(TkNode), ctypes.c_int, _ip],
+                      ctypes.c_int),
+    "tk_plan_stats": ([_vp, _u64p, _u64p], ctypes.c_int),
+    "tk_plan_workspace": ([_vp, ctypes.c_int, _u64p], ctypes.c_int),
+    "tk_plan_select": ([_vp, ctypes.c_int], ctypes.c_int),
+    "tk_plan_free": ([_vp], None),
+    "hooi_init": ([ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp, _vp,
+                   ctypes.POINTER(_vp)], ctypes.c_int),
+    "hooi_iterate": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "tucker_error": ([_vp, _dp, _dp, _dp], ctypes.c_int),
+    "tucker_error_explicit": ([_vp, _dp], ctypes.c_int),
+    "tk_get_factor": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "tk_get_core": ([_vp, _dp], ctypes.c_int),
+    "tk_set_factors": ([_vp, _dp], ctypes.c_int),
+    "tk_tree_pass": ([_vp], ctypes.c_int),
+    "tk_get_leaf": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "tk_get_gram": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "tk_profile_tree": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, _ip], ctypes.c_int),
+    "hooi_free": ([_vp], None),
+    "tk_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp],
+               ctypes.c_int),
+    "tk_gram": ([ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "tk_eig_leading": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
+                       ctypes.c_int),
+    "tk_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load libtucker.so (built by paper_1707_05594_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1707_05594_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc):
+    if rc != TK_OK:
+        raise TuckerError(rc, lib().tk_last_error().decode(errors="replace"))
+
+
+def _arr64(vals):
+    return (ctypes.c_int64 * len(vals))(*[int(v) for v in vals])
+
+
+# ----------------------------------------------------------------------------- planning --
+class Plan:
+    """A TTM-tree plan (host only).  Rank 0 is the selected tree unless select() is used."""
+
+    def __init__(self, handle, L, K):
+        self._h = handle
+        self.L = tuple(int(x) for x in L)
+        self.K = tuple(int(x) for x in K)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.tk_plan_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def count(self):
+        n = ctypes.c_int()
+        _check(lib().tk_plan_count(self._h, ctypes.byref(n)))
+        return n.value
+
+    def cost(self, rank=0):
+        c = ctypes.c_uint64()
+        _check(lib().tk_plan_cost(self._h, rank, ctypes.byref(c)))
+        return int(c.value)
+
+    def string(self, rank=0):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().tk_plan_string(self._h, rank, buf, len(buf)))
+        return buf.value.decode()
+
+    def nodes(self, rank=0):
+        n = ctypes.c_int()
+        _check(lib().tk_plan_nodes(self._h, rank, None, 0, ctypes.byref(n)))
+        arr = (TkNode * n.value)()
+        _check(lib().tk_plan_nodes(self._h, rank, arr, n.value, ctypes.byref(n)))
+        return [dict(parent=x.parent, mode=x.mode, is_leaf=bool(x.is_leaf), depth=x.depth,
+                     in_card=int(x.in_card), out_card=int(x.out_card), macs=int(x.macs),
+                     pre_mask=int(x.pre_mask)) for x in arr]
+
+    def stats(self):
+        e, l = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().tk_plan_stats(self._h, ctypes.byref(e), ctypes.byref(l)))
+        return int(e.value), int(l.value)
+
+    def workspace(self, rank=0):
+        w = ctypes.c_uint64()
+        _check(lib().tk_plan_workspace(self._h, rank, ctypes.byref(w)))
+        return int(w.value)
+
+    def select(self, rank):
+        _check(lib().tk_plan_select(self._h, rank))
+
+
+def ttm_tree_plan(L, K, kind="dp", topk=1) -> Plan:
+    """Plan a TTM-tree for lengths L and core lengths K (kind: dp, chain, chain_k,
+    chain_h, balanced)."""
+    h = _vp()
+    _check(lib().ttm_tree_plan(len(L), _arr64(L), _arr64(K), TREE_KINDS[kind], int(topk),
+                               ctypes.byref(h)))
+    return Plan(h, L, K)
+
+
+# ----------------------------------------------------------------------------- device side --
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    m = {torch.float64: TK_F64, torch.float32: TK_F32, torch.bfloat16: TK_BF16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _dev_ptr(t):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """HOOI context on a device tensor T (borrowed: keep T alive)."""
+
+    def __init__(self, T, K, plan=None, compute="fp32", F0=None, stream=None):
+        import numpy as np
+        self.T = T
+        self.L = tuple(int(x) for x in T.shape)
+        self.K = tuple(int(x) for x in K)
+        self.N = len(self.L)
+        self._stream = stream
+        f0p = None
+        if F0 is not None:
+            flat = np.concatenate([np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+                                   for f in F0])
+            self._f0 = flat
+            f0p = flat.ctypes.data_as(_dp)
+        h = _vp()
+        _check(lib().hooi_init(self.N, _arr64(self.L), _arr64(self.K), _dtype_code(T),
+                               _dev_ptr(T), plan.handle if plan is not None else None,
+                               COMPUTE[compute] if isinstance(compute, str) else int(compute),
+                               f0p, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hooi_free(self._h)
+            self._h = None
+
+    def iterate(self, iters=1):
+        errs = (ctypes.c_double * iters)()
+        _check(lib().hooi_iterate(self._h, iters, errs))
+        return list(errs)
+
+    def error(self):
+        e, nt, ng = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().tucker_error(self._h, ctypes.byref(e), ctypes.byref(nt), ctypes.byref(ng)))
+        return e.value, nt.value, ng.value
+
+    def error_explicit(self):
+        e = ctypes.c_double()
+        _check(lib().tucker_error_explicit(self._h, ctypes.byref(e)))
+        return e.value
+
+    def factor(self, n):
+        import numpy as np
+        out = np.empty((self.L[n], self.K[n]), dtype=np.float64)
+        _check(lib().tk_get_factor(self._h, n, out.ctypes.data_as(_dp)))
+        return out
+
+    def factors(self):
+        return [self.factor(n) for n in range(self.N)]
+
+    def core(self):
+        import numpy as np
+        out = np.empty(self.K, dtype=np.float64)
+        _check(lib().tk_get_core(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def set_factors(self, F):
+        import numpy as np
+        flat = np.concatenate([np.ascontiguousarray(f, dtype=np.float64).reshape(-1) for f in F])
+        _check(lib().tk_set_factors(self._h, flat.ctypes.data_as(_dp)))
+
+    def tree_pass(self):
+        _check(lib().tk_tree_pass(self._h))
+
+    def leaf(self, n):
+        import numpy as np
+        shape = tuple(self.L[j] if j == n else self.K[j] for j in range(self.N))
+        out = np.empty(shape, dtype=np.float64)
+        _check(lib().tk_get_leaf(self._h, n, out.ctypes.data_as(_dp)))
+        return out
+
+    def gram(self, n):
+        import numpy as np
+        out = np.empty((self.L[n], self.L[n]), dtype=np.float64)
+        _check(lib().tk_get_gram(self._h, n, out.ctypes.data_as(_dp)))
+        return out
+
+    def profile_tree(self):
+        n = ctypes.c_int()
+        _check(lib().tk_profile_tree(self._h, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_float * n.value)()
+        _check(lib().tk_profile_tree(self._h, arr, n.value, ctypes.byref(n)))
+        return list(arr)
+
+
+def hooi_init(T, K, plan=None, compute="fp32", F0=None, stream=None) -> Context:
+    """Create a HOOI context: HOSVD start unless F0 (list of L_n x K_n) is given."""
+    return Context(T, K, plan=plan, compute=compute, F0=F0, stream=stream)
+
+
+def hooi_iterate(ctx: Context, iters=1):
+    """Run `iters` HOOI invocations; returns the relative error after each."""
+    return ctx.iterate(iters)
+
+
+def tucker_error(ctx: Context):
+    """(relative error, ||T||, ||G||) of the current decomposition."""
+    return ctx.error()
+
+
+# ----------------------------------------------------------------------------- kernel level --
+def ttm(inp, A, L, B, F, K, out, compute="fp32", stream=None):
+    """Out[a,k,b] = sum_l F[l,k] In[a,l,b] on device tensors."""
+    _check(lib().tk_ttm(_dtype_code(inp), COMPUTE[compute], _dev_ptr(inp), int(A), int(L),
+                        int(B), _dev_ptr(F), int(K), _dev_ptr(out), _stream_ptr(stream)))
+
+
+def gram(Y, A, L, B, S, stream=None):
+    """S (L x L FP64, device) = Gram of the mode unfolding of Y viewed as [A, L, B]."""
+    _check(lib().tk_gram(_dtype_code(Y), _dev_ptr(Y), int(A), int(L), int(B), _dev_ptr(S),
+                         _stream_ptr(stream)))
+
+
+def eig_leading(S, K, V0=None, F=None, evals=None, stream=None):
+    """Leading K eigenpairs of count x L x L symmetric FP64 device matrices."""
+    torch = _torch()
+    if S.dim() == 2:
+        S = S.unsqueeze(0)
+    count, L, _ = S.shape
+    if F is None:
+        F = torch.empty((count, L, K), dtype=torch.float64, device=S.device)
+    if evals is None:
+        evals = torch.empty((count, K), dtype=torch.float64, device=S.device)
+    _check(lib().tk_eig_leading(count, L, K, _dev_ptr(S),
+                                _dev_ptr(V0) if V0 is not None else None, _dev_ptr(F),
+                                _dev_ptr(evals), _stream_ptr(stream)))
+    return F, evals

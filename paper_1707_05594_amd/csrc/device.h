@@ -1,0 +1,61 @@
+// Device-side helpers shared by the HIP sources of libtucker (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// bfloat16 is carried as its 16-bit pattern.
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+// Round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+struct Elem;
+template <>
+struct Elem<float> {
+  __device__ __forceinline__ static float to_f32(float v) { return v; }
+  __device__ __forceinline__ static double to_f64(float v) { return (double)v; }
+};
+template <>
+struct Elem<double> {
+  __device__ __forceinline__ static float to_f32(double v) { return (float)v; }
+  __device__ __forceinline__ static double to_f64(double v) { return v; }
+};
+template <>
+struct Elem<uint16_t> {
+  __device__ __forceinline__ static float to_f32(uint16_t v) { return bf16_to_f32(v); }
+  __device__ __forceinline__ static double to_f64(uint16_t v) { return (double)bf16_to_f32(v); }
+};
+
+// Four consecutive elements starting at a 4-element-aligned index, as FP32.
+__device__ __forceinline__ f4 load4_f32(const float* p) {
+  return *reinterpret_cast<const f4*>(p);
+}
+__device__ __forceinline__ f4 load4_f32(const uint16_t* p) {
+  uint2 v = *reinterpret_cast<const uint2*>(p);
+  f4 r;
+  r[0] = __uint_as_float(v.x << 16);
+  r[1] = __uint_as_float(v.x & 0xFFFF0000u);
+  r[2] = __uint_as_float(v.y << 16);
+  r[3] = __uint_as_float(v.y & 0xFFFF0000u);
+  return r;
+}
+
+// Wave-level sum (64 lanes) of a double, result valid in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace tk

@@ -1,0 +1,757 @@
+// HOOI engine: device context, depth-first TTM-tree executor, HOSVD start,
+// factor update, core and error (Fig. 2 "HOOI Procedure"; Sec. 3.1 tree
+// execution; Sec. 5 Gram + EVD).
+//
+// Tree execution (Sec. 3.1): nodes run in depth-first order, a node's input is
+// its parent's output, and a node's output is reused by all its children.
+// Outputs live on a stack: the output of a node at depth d sits right after
+// the outputs of its ancestors, so at most one intermediate per depth is alive
+// and the workspace is the largest per-path sum of |Out(u)|.
+//
+// One HOOI invocation (Jacobi form: every chain uses the factors from the
+// start of the invocation):
+//   tree pass with F^(t): every leaf n gets Y_n, its Gram S_n is formed;
+//   the core of decomposition t is folded in, G^(t) = Y_m x_m F_m^(t)T for the
+//   leaf m with the smallest Y (all chains agree by commutativity), and
+//   ||G^(t)||^2 gives the error of decomposition t;
+//   FP64 eigensolver (warm-started from F^(t)) -> F^(t+1).
+// The core of the final decomposition comes from a direct TTM chain over T in
+// the cheapest order for a single chain (ascending K_j L_j / (L_j - K_j)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using namespace tk;
+
+namespace {
+
+#define TK_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(TK_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
+  } while (0)
+
+int dalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(TK_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return TK_OK;
+}
+
+size_t dtype_size(int dt) { return dt == TK_F64 ? 8 : (dt == TK_F32 ? 4 : 2); }
+
+int64_t align64(int64_t x) { return (x + 63) & ~(int64_t)63; }
+
+// [A, L, B] view of a tensor whose modes in `pre` are already multiplied, along mode n.
+void view(const Shape& s, uint32_t pre, int n, int64_t* A, int64_t* L, int64_t* B) {
+  int64_t a = 1, b = 1;
+  for (int j = 0; j < s.N; ++j) {
+    const int64_t d = ((pre >> j) & 1u) ? s.K[j] : s.L[j];
+    if (j < n) a *= d;
+    if (j > n) b *= d;
+  }
+  *A = a;
+  *L = ((pre >> n) & 1u) ? s.K[n] : s.L[n];
+  *B = b;
+}
+
+}  // namespace
+
+struct tk_ctx {
+  Shape s;
+  int tdtype = TK_F32;
+  int compute = TK_C_FP32;
+  int wdtype = TK_F32;  // element type of intermediates and compute-precision factors
+  const void* T = nullptr;
+  hipStream_t st = nullptr;
+  Tree tree;
+  std::vector<int64_t> node_off;  // element offset of each internal node's output in ws
+  std::vector<int> chain_order;   // mode order of the direct core chain
+  int fold_leaf = 0;              // leaf whose Y folds the core
+  int64_t ws_elems = 0, chain_a = 0;
+  size_t fofs[TK_MAX_MODES + 1] = {};
+  size_t sofs[TK_MAX_MODES + 1] = {};
+  size_t kofs[TK_MAX_MODES + 1] = {};
+  int64_t core_elems = 1;
+
+  void* ws = nullptr;
+  double* F64a = nullptr;   // current factors (FP64 master)
+  double* F64b = nullptr;   // next factors
+  void* Fc = nullptr;       // compute-precision copy of the current factors
+  double* S = nullptr;      // Gram matrices
+  double* ev = nullptr;     // eigenvalues
+  double* eigwork = nullptr;
+  int* status = nullptr;
+  EigJob* jobs = nullptr;   // device job table, warm start from F64a
+  EigJob* jobs_cold = nullptr;
+  std::vector<EigJob> jobs_h;
+  double* gpart = nullptr;  // Gram chunk partials
+  size_t gpart_elems = 0;
+  double* rpart = nullptr;  // reduction partials
+  double* scal = nullptr;   // device scalars: [0] ||T||^2, [1..] ||G||^2 history
+  int scal_cap = 0;
+  void* core = nullptr;     // core of the current decomposition (wdtype)
+  std::vector<void*> leaves;  // optional copies of leaf tensors (tk_tree_pass)
+  std::vector<int64_t> leaf_elems;
+
+  double normT2 = 0.0;
+  double normG2 = 0.0;
+  bool core_valid = false;
+  int maxit_warm = 30, maxit_cold = 200;
+  double eig_tol = 1e-11;
+
+  ~tk_ctx() {
+    void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc, S, ev, eigwork, status, jobs,
+                    jobs_cold, gpart, rpart, scal, core};
+    for (void* p : ptrs)
+      if (p) (void)hipFree(p);
+    for (void* p : leaves)
+      if (p) (void)hipFree(p);
+  }
+
+  const void* fc(int n) const {
+    return (const char*)Fc + fofs[n] * dtype_size(wdtype);
+  }
+  void* wsp(int64_t off) const { return (char*)ws + off * dtype_size(wdtype); }
+};
+
+namespace {
+
+int run_eig(tk_ctx* c, bool warm, double* F_out, int maxit) {
+  TK_HIP(launch_eig(c->s.N, warm ? c->jobs : c->jobs_cold, c->S, c->F64a, F_out, c->ev,
+                    c->eigwork, c->status, maxit, c->eig_tol, c->st));
+  return TK_OK;
+}
+
+int refresh_compute_factors(tk_ctx* c) {
+  if (c->wdtype == TK_F64) return TK_OK;  // Fc aliases F64a in FP64 mode
+  TK_HIP(launch_convert(TK_F64, c->wdtype, c->F64a, c->Fc, (int64_t)c->fofs[c->s.N], c->st));
+  return TK_OK;
+}
+
+int check_status(tk_ctx* c) {
+  std::vector<int> st(c->s.N);
+  TK_HIP(hipMemcpyAsync(st.data(), c->status, sizeof(int) * c->s.N, hipMemcpyDeviceToHost, c->st));
+  TK_HIP(hipStreamSynchronize(c->st));
+  for (int n = 0; n < c->s.N; ++n) {
+    if (st[n] == 2) return fail(TK_ENUMERIC, "non-finite values in the eigensolver for mode %d", n);
+    if (st[n] == 1)
+      return fail(TK_ENUMERIC, "eigensolver did not converge for mode %d (no gap at K?)", n);
+  }
+  return TK_OK;
+}
+
+// One tree pass with the compute-precision factors in c->Fc.
+//   fold_dst >= 0: fold the core (G = Y_m x_m F_m^T) and store ||G||^2 in scal[fold_dst].
+//   keep: copy every leaf tensor to c->leaves.
+//   ev_t: optional per-node timing events (2 per node).
+int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t) {
+  const Shape& s = c->s;
+  const auto& nodes = c->tree.nodes;
+  for (size_t u = 0; u < nodes.size(); ++u) {
+    const tk_node& nd = nodes[u];
+    const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
+    const int in_dt = nd.parent < 0 ? c->tdtype : c->wdtype;
+    int64_t A, L, B;
+    view(s, nd.pre_mask, nd.mode, &A, &L, &B);
+    if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
+    if (!nd.is_leaf) {
+      TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
+                        c->wsp(c->node_off[u]), c->st));
+    } else {
+      const int n = nd.mode;
+      TK_HIP(launch_gram(in_dt, in, A, L, B, c->S + c->sofs[n], c->gpart, c->st));
+      if (keep)
+        TK_HIP(hipMemcpyAsync(c->leaves[n], in, (size_t)c->leaf_elems[n] * dtype_size(in_dt),
+                              hipMemcpyDeviceToDevice, c->st));
+      if (fold_dst >= 0 && n == c->fold_leaf) {
+        TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
+        TK_HIP(launch_sumsq(c->wdtype, c->core, c->core_elems, c->rpart, c->scal + fold_dst,
+                            c->st));
+      }
+    }
+    if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u + 1], c->st));
+  }
+  return TK_OK;
+}
+
+// Core of the current factors by a direct chain over T; ||G||^2 -> scal[dst].
+int core_chain(tk_ctx* c, int dst) {
+  const Shape& s = c->s;
+  uint32_t pre = 0;
+  const void* in = c->T;
+  int in_dt = c->tdtype;
+  const int N = s.N;
+  for (int i = 0; i < N; ++i) {
+    const int n = c->chain_order[i];
+    int64_t A, L, B;
+    view(s, pre, n, &A, &L, &B);
+    void* out = (i == N - 1) ? c->core : c->wsp((i % 2 == 0) ? 0 : c->chain_a);
+    TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], out, c->st));
+    pre |= 1u << n;
+    in = out;
+    in_dt = c->wdtype;
+  }
+  TK_HIP(launch_sumsq(c->wdtype, c->core, c->core_elems, c->rpart, c->scal + dst, c->st));
+  return TK_OK;
+}
+
+double rel_err_of(double normT2, double normG2) {
+  return std::sqrt(std::max(normT2 - normG2, 0.0) / normT2);
+}
+
+int ensure_scal(tk_ctx* c, int need) {
+  if (need <= c->scal_cap) return TK_OK;
+  if (c->scal) (void)hipFree(c->scal);
+  c->scal = nullptr;
+  const int cap = std::max(need, 64);
+  if (int rc = dalloc((void**)&c->scal, sizeof(double) * cap)) return rc;
+  c->scal_cap = cap;
+  return TK_OK;
+}
+
+}  // namespace
+
+extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, const void* T_dev,
+                         const tk_plan* plan, int compute, const double* F0_host, void* stream,
+                         tk_ctx** out) {
+  clear_error();
+  if (!out) return fail(TK_EINVAL, "out is null");
+  *out = nullptr;
+  Shape s;
+  if (int rc = make_shape(N, L, K, &s)) return rc;
+  if (!T_dev) return fail(TK_EINVAL, "T_dev is null");
+  if (tdtype < TK_F64 || tdtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
+    return fail(TK_EINVAL, "unknown compute mode %d", compute);
+  if ((tdtype == TK_F64) != (compute == TK_C_FP64))
+    return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
+  if (compute == TK_C_BF16 || compute == TK_C_BF16X3)
+    return fail(TK_EUNSUPPORTED, "compute mode %d is not built", compute);
+  const int maxL = compute == TK_C_FP64 ? 512 : ttm_max_L();
+  for (int j = 0; j < N; ++j) {
+    if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
+    if (s.K[j] > eig_max_K())
+      return fail(TK_EUNSUPPORTED, "K[%d]=%lld exceeds %d", j, (long long)s.K[j], eig_max_K());
+  }
+  if (plan && !plan->shape.same(s)) return fail(TK_EINVAL, "plan was built for another shape");
+
+  tk_ctx* c = new (std::nothrow) tk_ctx;
+  if (!c) return fail(TK_ENOMEM, "context allocation failed");
+  c->s = s;
+  c->tdtype = tdtype;
+  c->compute = compute;
+  c->wdtype = compute == TK_C_FP64 ? TK_F64 : TK_F32;
+  c->T = T_dev;
+  c->st = (hipStream_t)stream;
+  auto bail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+
+  // ---- plan
+  if (plan) {
+    c->tree = plan->trees[std::min<int>(plan->selected, (int)plan->trees.size() - 1)];
+  } else {
+    tk_plan* p = nullptr;
+    if (int rc = ttm_tree_plan(N, L, K, TK_TREE_DP, 1, &p)) return bail(rc);
+    c->tree = p->trees[0];
+    tk_plan_free(p);
+  }
+  const auto& nodes = c->tree.nodes;
+  c->node_off.assign(nodes.size(), 0);
+  int64_t ws = 0;
+  int64_t best_leaf = -1;
+  for (size_t u = 0; u < nodes.size(); ++u) {
+    const tk_node& nd = nodes[u];
+    // 64-element (>= 256-byte) alignment keeps the kernels' vector loads aligned
+    const int64_t base =
+        nd.parent < 0 ? 0 : align64(c->node_off[nd.parent] + (int64_t)nodes[nd.parent].out_card);
+    c->node_off[u] = base;
+    if (!nd.is_leaf) ws = std::max<int64_t>(ws, base + (int64_t)nd.out_card);
+  }
+  // leaf that folds the core: the smallest Y (ties: lowest mode)
+  for (int n = 0; n < N; ++n) {
+    const int64_t y = (int64_t)s.card(((1u << N) - 1) & ~(1u << n));
+    if (best_leaf < 0 || y < best_leaf) {
+      best_leaf = y;
+      c->fold_leaf = n;
+    }
+  }
+  // direct core chain order: ascending K L / (L - K), modes with K = L last
+  c->chain_order.resize(N);
+  for (int j = 0; j < N; ++j) c->chain_order[j] = j;
+  std::stable_sort(c->chain_order.begin(), c->chain_order.end(), [&](int a, int b) {
+    const bool fa = s.K[a] == s.L[a], fb = s.K[b] == s.L[b];
+    if (fa != fb) return !fa;
+    if (fa) return false;
+    return (__int128)s.K[a] * s.L[a] * (s.L[b] - s.K[b]) <
+           (__int128)s.K[b] * s.L[b] * (s.L[a] - s.K[a]);
+  });
+  {
+    const int o0 = c->chain_order[0], o1 = c->chain_order[1];
+    const int64_t out1 = (int64_t)(s.card_T() / s.L[o0] * s.K[o0]);
+    const int64_t out2 = out1 / s.L[o1] * s.K[o1];
+    c->chain_a = align64(out1);
+    ws = std::max<int64_t>(ws, c->chain_a + out2);
+  }
+  c->ws_elems = ws;
+  for (int n = 0; n < N; ++n) {
+    c->fofs[n + 1] = c->fofs[n] + (size_t)(s.L[n] * s.K[n]);
+    c->sofs[n + 1] = c->sofs[n] + (size_t)(s.L[n] * s.L[n]);
+    c->kofs[n + 1] = c->kofs[n] + (size_t)s.K[n];
+    c->core_elems *= s.K[n];
+  }
+
+  // ---- eigensolver jobs
+  size_t work = 0;
+  c->jobs_h.resize(N);
+  for (int n = 0; n < N; ++n) {
+    EigJob& j = c->jobs_h[n];
+    const int64_t rank_bound = (int64_t)(s.card(((1u << N) - 1) & ~(1u << n)) / s.L[n]);
+    j.L = (int)s.L[n];
+    j.K = (int)s.K[n];
+    j.p = eig_block_size(j.L, j.K, rank_bound);
+    j.pad_ = 0;
+    j.S_off = (int64_t)c->sofs[n];
+    j.V0_off = (int64_t)c->fofs[n];
+    j.F_off = (int64_t)c->fofs[n];
+    j.ev_off = (int64_t)c->kofs[n];
+    j.work_off = (int64_t)work;
+    work += (size_t)2 * j.L * j.p;
+  }
+  std::vector<EigJob> cold = c->jobs_h;
+  for (auto& j : cold) j.V0_off = -1;
+
+  // ---- Gram workspace: leaves and the HOSVD unfoldings of T
+  size_t gp = 0;
+  for (int n = 0; n < N; ++n) {
+    gp = std::max(gp, gram_workspace_elems(s.L[n], (int64_t)(s.card(((1u << N) - 1) & ~(1u << n)) / s.L[n])));
+    if (!F0_host) gp = std::max(gp, gram_workspace_elems(s.L[n], (int64_t)(s.card_T() / s.L[n])));
+  }
+  c->gpart_elems = gp;
+
+  // ---- allocations
+  const size_t wsz = dtype_size(c->wdtype);
+  int rc = TK_OK;
+  if ((rc = dalloc(&c->ws, (size_t)c->ws_elems * wsz))) return bail(rc);
+  if ((rc = dalloc((void**)&c->F64a, sizeof(double) * c->fofs[N]))) return bail(rc);
+  if ((rc = dalloc((void**)&c->F64b, sizeof(double) * c->fofs[N]))) return bail(rc);
+  if (c->wdtype != TK_F64) {
+    if ((rc = dalloc(&c->Fc, wsz * c->fofs[N]))) return bail(rc);
+  }
+  if ((rc = dalloc((void**)&c->S, sizeof(double) * c->sofs[N]))) return bail(rc);
+  if ((rc = dalloc((void**)&c->ev, sizeof(double) * c->kofs[N]))) return bail(rc);
+  if ((rc = dalloc((void**)&c->eigwork, sizeof(double) * work))) return bail(rc);
+  if ((rc = dalloc((void**)&c->status, sizeof(int) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->jobs, sizeof(EigJob) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->jobs_cold, sizeof(EigJob) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->gpart, sizeof(double) * c->gpart_elems))) return bail(rc);
+  if ((rc = dalloc((void**)&c->rpart, sizeof(double) * sumsq_partials()))) return bail(rc);
+  if ((rc = ensure_scal(c, 64))) return bail(rc);
+  if ((rc = dalloc(&c->core, wsz * (size_t)c->core_elems))) return bail(rc);
+  if (c->wdtype == TK_F64) c->Fc = nullptr;
+
+  {
+    hipError_t e = hipMemcpyAsync(c->jobs, c->jobs_h.data(), sizeof(EigJob) * N,
+                                  hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->jobs_cold, cold.data(), sizeof(EigJob) * N, hipMemcpyHostToDevice,
+                         c->st);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(TK_EDEVICE, "job upload failed: %s", hipGetErrorString(e));
+    }
+  }
+
+  // ---- ||T||^2
+  if (hipError_t e = launch_sumsq(tdtype, T_dev, (int64_t)s.card_T(), c->rpart, c->scal, c->st);
+      e != hipSuccess) {
+    delete c;
+    return fail(TK_EDEVICE, "sum of squares of T failed: %s", hipGetErrorString(e));
+  }
+
+  // ---- starting factors
+  if (F0_host) {
+    for (size_t i = 0; i < c->fofs[N]; ++i)
+      if (!std::isfinite(F0_host[i])) return bail(fail(TK_ENUMERIC, "F0 holds NaN/Inf"));
+    if (hipError_t e = hipMemcpyAsync(c->F64a, F0_host, sizeof(double) * c->fofs[N],
+                                      hipMemcpyHostToDevice, c->st);
+        e != hipSuccess) {
+      delete c;
+      return fail(TK_EDEVICE, "factor upload failed: %s", hipGetErrorString(e));
+    }
+  } else {
+    // HOSVD: F_n = leading K_n left singular vectors of T_(n)
+    for (int n = 0; n < N; ++n) {
+      int64_t A, Ln, B;
+      view(s, 0, n, &A, &Ln, &B);
+      if (hipError_t e = launch_gram(tdtype, T_dev, A, Ln, B, c->S + c->sofs[n], c->gpart, c->st);
+          e != hipSuccess) {
+        delete c;
+        return fail(TK_EDEVICE, "HOSVD Gram failed: %s", hipGetErrorString(e));
+      }
+    }
+    if (hipError_t e = launch_fill_int(c->status, N, 0, c->st); e != hipSuccess) {
+      delete c;
+      return fail(TK_EDEVICE, "status reset failed: %s", hipGetErrorString(e));
+    }
+    if ((rc = run_eig(c, false, c->F64a, c->maxit_cold))) return bail(rc);
+    if ((rc = check_status(c))) return bail(rc);
+  }
+  if (c->wdtype == TK_F64) c->Fc = c->F64a;
+  if ((rc = refresh_compute_factors(c))) return bail(rc);
+  double nt2 = 0.0;
+  if (hipError_t e = hipMemcpyAsync(&nt2, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st);
+      e != hipSuccess) {
+    delete c;
+    return fail(TK_EDEVICE, "readback failed: %s", hipGetErrorString(e));
+  }
+  if (hipError_t e = hipStreamSynchronize(c->st); e != hipSuccess) {
+    delete c;
+    return fail(TK_EDEVICE, "hooi_init: %s", hipGetErrorString(e));
+  }
+  if (!(nt2 > 0.0) || !std::isfinite(nt2)) return bail(fail(TK_ENUMERIC, "||T|| is zero or not finite"));
+  c->normT2 = nt2;
+  *out = c;
+  return TK_OK;
+}
+
+extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
+  clear_error();
+  if (!c) return fail(TK_EINVAL, "ctx is null");
+  if (iters < 1) return fail(TK_EINVAL, "iters=%d < 1", iters);
+  if (int rc = ensure_scal(c, iters + 2)) return rc;
+  // scal[0] = ||T||^2 (kept), scal[1 + t] = ||G^(t)||^2, t = 0..iters
+  TK_HIP(launch_fill_int(c->status, c->s.N, 0, c->st));
+  for (int t = 0; t < iters; ++t) {
+    if (int rc = tree_pass(c, 1 + t, false, nullptr)) return rc;
+    if (int rc = run_eig(c, true, c->F64b, c->maxit_warm)) return rc;
+    std::swap(c->F64a, c->F64b);
+    if (c->wdtype == TK_F64) c->Fc = c->F64a;
+    if (int rc = refresh_compute_factors(c)) return rc;
+  }
+  if (int rc = core_chain(c, 1 + iters)) return rc;
+  std::vector<double> g2(iters + 1);
+  TK_HIP(hipMemcpyAsync(g2.data(), c->scal + 1, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost,
+                        c->st));
+  if (int rc = check_status(c)) return rc;  // synchronises
+  for (int t = 0; t < iters; ++t)
+    if (rel_err) rel_err[t] = rel_err_of(c->normT2, g2[t + 1]);
+  c->normG2 = g2[iters];
+  c->core_valid = true;
+  return TK_OK;
+}
+
+extern "C" int tucker_error(tk_ctx* c, double* rel_err, double* normT, double* normG) {
+  clear_error();
+  if (!c) return fail(TK_EINVAL, "ctx is null");
+  if (!c->core_valid) {
+    if (int rc = core_chain(c, 1)) return rc;
+    double g2 = 0.0;
+    TK_HIP(hipMemcpyAsync(&g2, c->scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->st));
+    TK_HIP(hipStreamSynchronize(c->st));
+    c->normG2 = g2;
+    c->core_valid = true;
+  }
+  if (rel_err) *rel_err = rel_err_of(c->normT2, c->normG2);
+  if (normT) *normT = std::sqrt(c->normT2);
+  if (normG) *normG = std::sqrt(c->normG2);
+  return TK_OK;
+}
+
+extern "C" int tucker_error_explicit(tk_ctx* c, double* rel_err) {
+  clear_error();
+  if (!c || !rel_err) return fail(TK_EINVAL, "null argument");
+  if (int rc = tucker_error(c, nullptr, nullptr, nullptr)) return rc;
+  const Shape& s = c->s;
+  const int N = s.N;
+  // expand G along modes N-1 .. 1 in FP64: Zp has lengths K0, L1, ..., L_{N-1}
+  int64_t big = s.K[0];
+  for (int j = 1; j < N; ++j) big *= s.L[j];
+  double *bufA = nullptr, *bufB = nullptr, *Ft = nullptr, *part = nullptr;
+  int rc = TK_OK;
+  if ((rc = dalloc((void**)&bufA, sizeof(double) * big))) return rc;
+  if ((rc = dalloc((void**)&bufB, sizeof(double) * big))) {
+    (void)hipFree(bufA);
+    return rc;
+  }
+  size_t ftn = 0;
+  for (int j = 0; j < N; ++j) ftn = std::max(ftn, (size_t)(s.L[j] * s.K[j]));
+  if ((rc = dalloc((void**)&Ft, sizeof(double) * ftn)) ||
+      (rc = dalloc((void**)&part, sizeof(double) * (sumsq_partials() + 1)))) {
+    (void)hipFree(bufA);
+    (void)hipFree(bufB);
+    if (Ft) (void)hipFree(Ft);
+    return rc;
+  }
+  auto cleanup = [&]() {
+    (void)hipFree(bufA);
+    (void)hipFree(bufB);
+    (void)hipFree(Ft);
+    (void)hipFree(part);
+  };
+  hipError_t e = launch_convert(c->wdtype, TK_F64, c->core, bufA, c->core_elems, c->st);
+  std::vector<double> Fh, Fth;
+  uint32_t kmask = (1u << N) - 1;  // modes still at length K
+  double* cur = bufA;
+  double* nxt = bufB;
+  for (int j = N - 1; j >= 1 && e == hipSuccess; --j) {
+    Fh.resize((size_t)(s.L[j] * s.K[j]));
+    Fth.resize(Fh.size());
+    e = hipMemcpyAsync(Fh.data(), c->F64a + c->fofs[j], sizeof(double) * Fh.size(),
+                       hipMemcpyDeviceToHost, c->st);
+    if (e != hipSuccess) break;
+    e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) break;
+    // TTM with F_j (L_j x K_j): the kernel's factor argument is F_j^T (K_j x L_j)
+    for (int64_t l = 0; l < s.L[j]; ++l)
+      for (int64_t k = 0; k < s.K[j]; ++k) Fth[k * s.L[j] + l] = Fh[l * s.K[j] + k];
+    e = hipMemcpyAsync(Ft, Fth.data(), sizeof(double) * Fth.size(), hipMemcpyHostToDevice, c->st);
+    if (e != hipSuccess) break;
+    int64_t A = 1, B = 1;
+    for (int m = 0; m < N; ++m) {
+      const int64_t d = ((kmask >> m) & 1u) ? s.K[m] : s.L[m];
+      if (m < j) A *= d;
+      if (m > j) B *= d;
+    }
+    e = launch_ttm(TK_F64, TK_C_FP64, cur, A, s.K[j], B, Ft, s.L[j], nxt, c->st);
+    kmask &= ~(1u << j);
+    std::swap(cur, nxt);
+  }
+  double r2 = 0.0;
+  if (e == hipSuccess) {
+    const int64_t R = big / s.K[0];
+    e = launch_residual(c->tdtype, c->T, cur, c->F64a + c->fofs[0], (int)s.L[0], (int)s.K[0], R,
+                        part, part + sumsq_partials(), c->st);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&r2, part + sumsq_partials(), sizeof(double), hipMemcpyDeviceToHost,
+                       c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  cleanup();
+  if (e != hipSuccess) return fail(TK_EDEVICE, "explicit residual failed: %s", hipGetErrorString(e));
+  *rel_err = std::sqrt(r2 / c->normT2);
+  return TK_OK;
+}
+
+extern "C" int tk_get_factor(tk_ctx* c, int n, double* host) {
+  clear_error();
+  if (!c || !host) return fail(TK_EINVAL, "null argument");
+  if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
+  TK_HIP(hipMemcpyAsync(host, c->F64a + c->fofs[n], sizeof(double) * (c->fofs[n + 1] - c->fofs[n]),
+                        hipMemcpyDeviceToHost, c->st));
+  TK_HIP(hipStreamSynchronize(c->st));
+  return TK_OK;
+}
+
+extern "C" int tk_get_core(tk_ctx* c, double* host) {
+  clear_error();
+  if (!c || !host) return fail(TK_EINVAL, "null argument");
+  if (int rc = tucker_error(c, nullptr, nullptr, nullptr)) return rc;
+  if (c->wdtype == TK_F64) {
+    TK_HIP(hipMemcpyAsync(host, c->core, sizeof(double) * c->core_elems, hipMemcpyDeviceToHost, c->st));
+  } else {
+    std::vector<float> tmp(c->core_elems);
+    TK_HIP(hipMemcpyAsync(tmp.data(), c->core, sizeof(float) * c->core_elems, hipMemcpyDeviceToHost,
+                          c->st));
+    TK_HIP(hipStreamSynchronize(c->st));
+    for (int64_t i = 0; i < c->core_elems; ++i) host[i] = tmp[i];
+  }
+  TK_HIP(hipStreamSynchronize(c->st));
+  return TK_OK;
+}
+
+extern "C" int tk_set_factors(tk_ctx* c, const double* host) {
+  clear_error();
+  if (!c || !host) return fail(TK_EINVAL, "null argument");
+  for (size_t i = 0; i < c->fofs[c->s.N]; ++i)
+    if (!std::isfinite(host[i])) return fail(TK_ENUMERIC, "factors hold NaN/Inf");
+  TK_HIP(hipMemcpyAsync(c->F64a, host, sizeof(double) * c->fofs[c->s.N], hipMemcpyHostToDevice, c->st));
+  if (int rc = refresh_compute_factors(c)) return rc;
+  TK_HIP(hipStreamSynchronize(c->st));
+  c->core_valid = false;
+  return TK_OK;
+}
+
+extern "C" int tk_tree_pass(tk_ctx* c) {
+  clear_error();
+  if (!c) return fail(TK_EINVAL, "ctx is null");
+  const Shape& s = c->s;
+  if (c->leaves.empty()) {
+    c->leaves.assign(s.N, nullptr);
+    c->leaf_elems.assign(s.N, 0);
+    for (int n = 0; n < s.N; ++n) {
+      c->leaf_elems[n] = (int64_t)s.card(((1u << s.N) - 1) & ~(1u << n));
+      if (int rc = dalloc(&c->leaves[n], (size_t)c->leaf_elems[n] * 8)) return rc;
+    }
+  }
+  if (int rc = tree_pass(c, -1, true, nullptr)) return rc;
+  TK_HIP(hipStreamSynchronize(c->st));
+  return TK_OK;
+}
+
+extern "C" int tk_get_leaf(tk_ctx* c, int n, double* host) {
+  clear_error();
+  if (!c || !host) return fail(TK_EINVAL, "null argument");
+  if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
+  if (c->leaves.empty()) return fail(TK_EINVAL, "call tk_tree_pass first");
+  const int64_t m = c->leaf_elems[n];
+  // the leaf's parent is T itself only when N == 2 and the leaf hangs off the root
+  int dt = c->wdtype;
+  for (const tk_node& nd : c->tree.nodes)
+    if (nd.is_leaf && nd.mode == n && nd.parent < 0) dt = c->tdtype;
+  if (dt == TK_F64) {
+    TK_HIP(hipMemcpy(host, c->leaves[n], sizeof(double) * m, hipMemcpyDeviceToHost));
+  } else if (dt == TK_F32) {
+    std::vector<float> tmp(m);
+    TK_HIP(hipMemcpy(tmp.data(), c->leaves[n], sizeof(float) * m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) host[i] = tmp[i];
+  } else {
+    std::vector<uint16_t> tmp(m);
+    TK_HIP(hipMemcpy(tmp.data(), c->leaves[n], sizeof(uint16_t) * m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) {
+      uint32_t u = (uint32_t)tmp[i] << 16;
+      float f;
+      memcpy(&f, &u, 4);
+      host[i] = f;
+    }
+  }
+  return TK_OK;
+}
+
+extern "C" int tk_get_gram(tk_ctx* c, int n, double* host) {
+  clear_error();
+  if (!c || !host) return fail(TK_EINVAL, "null argument");
+  if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
+  TK_HIP(hipMemcpyAsync(host, c->S + c->sofs[n], sizeof(double) * (c->sofs[n + 1] - c->sofs[n]),
+                        hipMemcpyDeviceToHost, c->st));
+  TK_HIP(hipStreamSynchronize(c->st));
+  return TK_OK;
+}
+
+extern "C" int tk_profile_tree(tk_ctx* c, float* ms_out, int cap, int* n) {
+  clear_error();
+  if (!c || !n) return fail(TK_EINVAL, "null argument");
+  const size_t nn = c->tree.nodes.size();
+  *n = (int)nn;
+  if (!ms_out) return TK_OK;
+  std::vector<hipEvent_t> ev(2 * nn);
+  for (auto& e : ev) TK_HIP(hipEventCreate(&e));
+  int rc = tree_pass(c, -1, false, ev.data());
+  if (rc == TK_OK) {
+    hipError_t e = hipEventSynchronize(ev.back());
+    if (e != hipSuccess) rc = fail(TK_EDEVICE, "profile sync: %s", hipGetErrorString(e));
+  }
+  for (size_t u = 0; rc == TK_OK && u < nn && (int)u < cap; ++u) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, ev[2 * u], ev[2 * u + 1]);
+    if (e != hipSuccess) rc = fail(TK_EDEVICE, "event time: %s", hipGetErrorString(e));
+    ms_out[u] = ms;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+extern "C" void hooi_free(tk_ctx* c) { delete c; }
+
+// ---------------------------------------------------------------- kernel-level entry points --
+extern "C" int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
+                      const void* F, int64_t K, void* out, void* stream) {
+  clear_error();
+  if (!in || !F || !out) return fail(TK_EINVAL, "null pointer");
+  if (A < 1 || L < 1 || B < 1 || K < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (compute == TK_C_FP64) {
+    if (in_dtype != TK_F64) return fail(TK_EUNSUPPORTED, "FP64 compute needs FP64 input");
+    if (L > 512) return fail(TK_EUNSUPPORTED, "FP64 TTM supports L <= 512");
+  } else if (compute == TK_C_FP32) {
+    if (in_dtype == TK_F64) return fail(TK_EUNSUPPORTED, "FP32 compute takes F32/BF16 input");
+    if (L > ttm_max_L()) return fail(TK_EUNSUPPORTED, "L=%lld exceeds %d", (long long)L, ttm_max_L());
+  } else {
+    return fail(TK_EUNSUPPORTED, "compute mode %d is not built", compute);
+  }
+  if (K > 4096) return fail(TK_EUNSUPPORTED, "K > 4096");
+  if (A * B > ((int64_t)1 << 40)) return fail(TK_EINVAL, "tensor too large");
+  TK_HIP(launch_ttm(in_dtype, compute, in, A, L, B, F, K, out, (hipStream_t)stream));
+  return TK_OK;
+}
+
+extern "C" int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
+                       void* stream) {
+  clear_error();
+  if (!Y || !S) return fail(TK_EINVAL, "null pointer");
+  if (A < 1 || L < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+  if (L > 1024) return fail(TK_EUNSUPPORTED, "L > 1024");
+  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  const size_t gp = gram_workspace_elems(L, A * B);
+  double* part = nullptr;
+  if (int rc = dalloc((void**)&part, sizeof(double) * gp)) return rc;
+  hipError_t e = launch_gram(in_dtype, Y, A, L, B, S, part, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return fail(TK_EDEVICE, "gram: %s", hipGetErrorString(e));
+  return TK_OK;
+}
+
+extern "C" int tk_eig_leading(int count, int L, int K, const double* S, const double* V0, double* F,
+                              double* evals, void* stream) {
+  clear_error();
+  if (!S || !F || !evals) return fail(TK_EINVAL, "null pointer");
+  if (count < 1 || L < 1 || K < 1 || K > L) return fail(TK_EINVAL, "bad sizes");
+  if (L > 1024 || K > eig_max_K()) return fail(TK_EUNSUPPORTED, "L <= 1024 and K <= %d required", eig_max_K());
+  hipStream_t st = (hipStream_t)stream;
+  const int p = eig_block_size(L, K, L);
+  std::vector<EigJob> jobs(count);
+  for (int m = 0; m < count; ++m) {
+    EigJob& j = jobs[m];
+    j.L = L;
+    j.K = K;
+    j.p = p;
+    j.pad_ = 0;
+    j.S_off = (int64_t)m * L * L;
+    j.V0_off = V0 ? (int64_t)m * L * K : -1;
+    j.F_off = (int64_t)m * L * K;
+    j.ev_off = (int64_t)m * K;
+    j.work_off = (int64_t)m * 2 * L * p;
+  }
+  EigJob* jd = nullptr;
+  double* work = nullptr;
+  int* status = nullptr;
+  int rc = TK_OK;
+  if ((rc = dalloc((void**)&jd, sizeof(EigJob) * count))) return rc;
+  if ((rc = dalloc((void**)&work, sizeof(double) * 2 * (size_t)L * p * count)) ||
+      (rc = dalloc((void**)&status, sizeof(int) * count))) {
+    (void)hipFree(jd);
+    if (work) (void)hipFree(work);
+    return rc;
+  }
+  std::vector<int> sth(count, 0);
+  hipError_t e = hipMemcpyAsync(jd, jobs.data(), sizeof(EigJob) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_fill_int(status, count, 0, st);
+  if (e == hipSuccess) e = launch_eig(count, jd, S, V0, F, evals, work, status, V0 ? 30 : 200, 1e-11, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(sth.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(jd);
+  (void)hipFree(work);
+  (void)hipFree(status);
+  if (e != hipSuccess) return fail(TK_EDEVICE, "eig: %s", hipGetErrorString(e));
+  for (int m = 0; m < count; ++m)
+    if (sth[m] != 0) return fail(TK_ENUMERIC, "eigensolver status %d for matrix %d", sth[m], m);
+  return TK_OK;
+}

@@ -1,0 +1,60 @@
+// Internal declarations shared by the host-side sources of libtucker.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tucker.h"
+
+namespace tk {
+
+// Record the calling thread's last error and return `code`.
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+struct Shape {
+  int N = 0;
+  int64_t L[TK_MAX_MODES] = {};
+  int64_t K[TK_MAX_MODES] = {};
+  uint64_t card_T() const {
+    uint64_t c = 1;
+    for (int j = 0; j < N; ++j) c *= (uint64_t)L[j];
+    return c;
+  }
+  // |T[P]|: T after multiplying along the modes of bitmask P.
+  uint64_t card(uint32_t P) const {
+    uint64_t c = 1;
+    for (int j = 0; j < N; ++j) c *= (uint64_t)(((P >> j) & 1u) ? K[j] : L[j]);
+    return c;
+  }
+  bool same(const Shape& o) const {
+    if (N != o.N) return false;
+    for (int j = 0; j < N; ++j)
+      if (L[j] != o.L[j] || K[j] != o.K[j]) return false;
+    return true;
+  }
+};
+
+// Checks 2 <= N <= TK_MAX_MODES, 1 <= K_n <= L_n, K_n <= prod_{m!=n} K_m,
+// prod(L) < 2^62.  Fills `s`.  Returns TK_OK or TK_EINVAL (with message).
+int make_shape(int N, const int64_t* L, const int64_t* K, Shape* s);
+
+struct Tree {
+  std::vector<tk_node> nodes;  // depth-first execution order, parents first
+  uint64_t cost = 0;           // multiply-adds
+  std::string canon;           // canonical text
+};
+
+std::string canonical_string(const std::vector<tk_node>& nodes);
+uint64_t workspace_elements(const std::vector<tk_node>& nodes);
+
+}  // namespace tk
+
+struct tk_plan {
+  tk::Shape shape;
+  int kind = 0;
+  int selected = 0;  // rank used by hooi_init
+  std::vector<tk::Tree> trees;
+  uint64_t entries = 0, lookups = 0;
+};

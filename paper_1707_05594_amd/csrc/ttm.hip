@@ -1,0 +1,351 @@
+// TTM node kernels (Sec. 2.1): Out = In x_n F^T without unfolding.
+//
+// A node multiplies its input along mode n by the transpose of the L x K
+// factor F.  Seen row-major as [A, L, B] (A = product of the lengths before
+// mode n, B = after it) the operation is, for every "column" (a, b),
+//
+//     Out[a, k, b] = sum_l F[l, k] * In[a, l, b],      0 <= k < K,
+//
+// i.e. F^T applied to every mode-n fiber.  Columns with consecutive b are
+// contiguous in memory, so a wave that owns consecutive columns reads In with
+// unit stride (coalesced) for every l and writes Out the same way.
+//
+// FP32 arithmetic runs on v_mfma_f32_4x4x1_16b_f32: sixteen independent 4x4
+// outer products per instruction.  Block beta (lanes 4*beta..4*beta+3) takes
+// its 4 A-values (four k's of one F row, identical for every block) and 4
+// B-values (four columns, one per lane); lane i receives D[m][i%4] for
+// m = 0..3, i.e. four k's of its own column.  K is covered in groups of four,
+// so only K mod 4 rows are ever padded (K = 20 wastes nothing), unlike
+// 16- or 32-row tiles.  A lane loads four consecutive b of one row with one
+// 16-byte load and issues one MFMA per component, so each lane ends up with
+// four consecutive b for each k and stores them with one 16-byte store.
+//
+// FP64 arithmetic (FP64 storage) uses plain FP64 FMAs on an LDS-staged tile.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace tk {
+
+__device__ __forceinline__ f4 mfma4x4x1(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// Stage the factor slice used by this block in LDS as FT[r][l][g] = F[l, k0+4g+r]
+// (zero beyond K), so that lane i reads its A-values FT[i%4][l][0..KG-1]
+// contiguously.
+template <int KG>
+__device__ __forceinline__ void stage_factor(float* FT, const float* __restrict__ F, int L,
+                                             int Kt, int k0) {
+  const int total = 4 * L * KG;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int g = e % KG;
+    const int t = e / KG;
+    const int l = t % L;
+    const int r = t / L;
+    const int k = k0 + 4 * g + r;
+    FT[e] = (k < Kt) ? F[(int64_t)l * Kt + k] : 0.f;
+  }
+}
+
+// ------------------------------------------------------------------ wide path --
+// Requires B % 4 == 0.  A wave owns 256 consecutive columns; lane i owns
+// columns c0 + 4i .. c0 + 4i + 3 (same a, consecutive b).  grid.y splits K
+// into chunks of 4*KG rows.
+template <int KG, typename TIn>
+__global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t C, int L,
+                                                    int64_t B, int Kt) {
+  extern __shared__ float smem[];
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
+  if (((int64_t)blockIdx.x * 4 + wave) * 256 >= C) return;  // whole wave idle
+  const bool active = c < C;
+  const int64_t a = active ? c / B : 0;
+  const int64_t b = active ? c - a * B : 0;
+  const TIn* p = in + (a * L) * B + b;
+  const float* ft = smem + (lane & 3) * L * KG;
+
+  f4 acc[KG][4];
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int U = 4;
+  int l = 0;
+  for (; l + U <= L; l += U) {
+    f4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = active ? load4_f32(p + (int64_t)(l + u) * B) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        const float fa = ft[(l + u) * KG + g];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+      }
+    }
+  }
+  for (; l < L; ++l) {
+    const f4 x = active ? load4_f32(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const float fa = ft[l * KG + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[j], acc[g][j]);
+    }
+  }
+  if (!active) return;
+  float* q = out + (a * Kt) * B + b;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) {
+        f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
+        *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
+      }
+    }
+}
+
+// ------------------------------------------------------------------ tile path --
+// Any B.  A block owns a tile of na consecutive a's times nb consecutive b's
+// (na * nb <= 256 columns, one per thread).  The tile's rows of In are staged
+// through LDS in chunks of LC rows with loads in memory order (runs of nb
+// contiguous elements), then each thread reads its column from LDS.
+constexpr int kTileLC = 32;
+
+template <int KG, typename TIn>
+__global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t A, int L,
+                                                    int64_t B, int Kt, int na, int nb,
+                                                    int64_t nbt) {
+  extern __shared__ float smem[];
+  float* FT = smem;
+  float* X = smem + 4 * L * KG;  // [kTileLC][256]
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor<KG>(FT, F, L, Kt, k0);
+  const int64_t at = blockIdx.x / nbt;
+  const int64_t bt = blockIdx.x - at * nbt;
+  const int64_t a0 = at * na;
+  const int64_t b0 = bt * nb;
+  const int nav = (int)min((int64_t)na, A - a0);
+  const int nbv = (int)min((int64_t)nb, B - b0);
+  const int col = threadIdx.x;
+  const int a_loc = col / nb;
+  const int b_loc = col - a_loc * nb;
+  const bool active = a_loc < nav && b_loc < nbv;
+  const int lane = threadIdx.x & 63;
+  const float* ft = FT + (lane & 3) * L * KG;
+
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int l0 = 0; l0 < L; l0 += kTileLC) {
+    const int lc = min(kTileLC, L - l0);
+    __syncthreads();
+    const int total = nav * lc * nbv;
+    for (int e = threadIdx.x; e < total; e += 256) {
+      const int bb = e % nbv;
+      const int t = e / nbv;
+      const int ll = t % lc;
+      const int aa = t / lc;
+      X[ll * 256 + aa * nb + bb] =
+          Elem<TIn>::to_f32(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+    }
+    __syncthreads();
+    for (int ll = 0; ll < lc; ++ll) {
+      const float x = active ? X[ll * 256 + col] : 0.f;
+#pragma unroll
+      for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + ll) * KG + g], x, acc[g]);
+    }
+  }
+  if (!active) return;
+  float* q = out + ((a0 + a_loc) * Kt) * B + b0 + b_loc;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) q[(int64_t)k * B] = acc[g][m];
+    }
+}
+
+// ------------------------------------------------------------------ FP64 path --
+// Same tiling; each thread accumulates KC outputs of its column in FP64.
+constexpr int kF64LC = 16;
+
+template <int KC, typename TIn>
+__global__ __launch_bounds__(256) void ttm_tile_f64(const TIn* __restrict__ in,
+                                                    const double* __restrict__ F,
+                                                    double* __restrict__ out, int64_t A, int L,
+                                                    int64_t B, int Kt, int na, int nb,
+                                                    int64_t nbt) {
+  extern __shared__ double dsm[];
+  double* Fs = dsm;              // [L][KC]
+  double* X = dsm + L * KC;      // [kF64LC][256]
+  const int k0 = blockIdx.y * KC;
+  for (int e = threadIdx.x; e < L * KC; e += 256) {
+    const int kk = e % KC, l = e / KC;
+    Fs[e] = (k0 + kk < Kt) ? F[(int64_t)l * Kt + k0 + kk] : 0.0;
+  }
+  const int64_t at = blockIdx.x / nbt;
+  const int64_t bt = blockIdx.x - at * nbt;
+  const int64_t a0 = at * na;
+  const int64_t b0 = bt * nb;
+  const int nav = (int)min((int64_t)na, A - a0);
+  const int nbv = (int)min((int64_t)nb, B - b0);
+  const int col = threadIdx.x;
+  const int a_loc = col / nb;
+  const int b_loc = col - a_loc * nb;
+  const bool active = a_loc < nav && b_loc < nbv;
+  double acc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) acc[k] = 0.0;
+  for (int l0 = 0; l0 < L; l0 += kF64LC) {
+    const int lc = min(kF64LC, L - l0);
+    __syncthreads();
+    const int total = nav * lc * nbv;
+    for (int e = threadIdx.x; e < total; e += 256) {
+      const int bb = e % nbv;
+      const int t = e / nbv;
+      const int ll = t % lc;
+      const int aa = t / lc;
+      X[ll * 256 + aa * nb + bb] =
+          Elem<TIn>::to_f64(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+    }
+    __syncthreads();
+    if (active) {
+      for (int ll = 0; ll < lc; ++ll) {
+        const double x = X[ll * 256 + col];
+        const double* fr = Fs + (l0 + ll) * KC;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) acc[k] = fma(fr[k], x, acc[k]);
+      }
+    }
+  }
+  if (!active) return;
+  double* q = out + ((a0 + a_loc) * Kt) * B + b0 + b_loc;
+#pragma unroll
+  for (int k = 0; k < KC; ++k)
+    if (k0 + k < Kt) q[(int64_t)(k0 + k) * B] = acc[k];
+}
+
+// ------------------------------------------------------------------ launchers --
+namespace {
+
+constexpr int kLdsBudget = 64 * 1024;
+
+template <typename TIn, int KG>
+hipError_t launch_f32_kg(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
+                         float* out, hipStream_t st) {
+  const int chunks = (K + 4 * KG - 1) / (4 * KG);
+  const int64_t C = A * B;
+  const bool aligned = ((uintptr_t)in % (4 * sizeof(TIn)) == 0) && ((uintptr_t)out % 16 == 0);
+  if (B % 4 == 0 && B >= 16 && aligned) {
+    const size_t lds = (size_t)16 * L * KG;
+    const int64_t blocks = (C + 1023) / 1024;
+    dim3 grid((unsigned)blocks, (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_wide_f32<KG, TIn>), grid, dim3(256), lds, st, in, F, out, C, L, B,
+                       K);
+  } else {
+    const int nb = (int)std::min<int64_t>(B, 256);
+    const int na = 256 / nb;
+    const int64_t nbt = (B + nb - 1) / nb;
+    const int64_t nat = (A + na - 1) / na;
+    const size_t lds = (size_t)16 * L * KG + (size_t)4 * kTileLC * 256;
+    dim3 grid((unsigned)(nat * nbt), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_tile_f32<KG, TIn>), grid, dim3(256), lds, st, in, F, out, A, L, B,
+                       K, na, nb, nbt);
+  }
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
+                      float* out, hipStream_t st) {
+  // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path):
+  // the smallest instance covering ceil(K/4) groups if it fits, else the
+  // largest that fits (K is then covered by several chunks).
+  static const int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
+  const int need = (K + 3) / 4;
+  const int kg_cap = std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L));
+  int kg = 1;
+  for (int c : kInst)
+    if (c <= kg_cap) kg = c;  // largest fitting instance
+  for (int c : kInst)
+    if (c >= need && c <= kg_cap) {
+      kg = c;
+      break;
+    }
+  switch (kg) {
+    case 1: return launch_f32_kg<TIn, 1>(in, A, L, B, F, K, out, st);
+    case 2: return launch_f32_kg<TIn, 2>(in, A, L, B, F, K, out, st);
+    case 3: return launch_f32_kg<TIn, 3>(in, A, L, B, F, K, out, st);
+    case 4: return launch_f32_kg<TIn, 4>(in, A, L, B, F, K, out, st);
+    case 5: return launch_f32_kg<TIn, 5>(in, A, L, B, F, K, out, st);
+    case 6: return launch_f32_kg<TIn, 6>(in, A, L, B, F, K, out, st);
+    case 8: return launch_f32_kg<TIn, 8>(in, A, L, B, F, K, out, st);
+    case 12: return launch_f32_kg<TIn, 12>(in, A, L, B, F, K, out, st);
+    default: return launch_f32_kg<TIn, 16>(in, A, L, B, F, K, out, st);
+  }
+}
+
+template <int KC>
+hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const double* F, int K,
+                         double* out, hipStream_t st) {
+  const int chunks = (K + KC - 1) / KC;
+  const int nb = (int)std::min<int64_t>(B, 256);
+  const int na = 256 / nb;
+  const int64_t nbt = (B + nb - 1) / nb;
+  const int64_t nat = (A + na - 1) / na;
+  const size_t lds = (size_t)8 * L * KC + (size_t)8 * kF64LC * 256;
+  dim3 grid((unsigned)(nat * nbt), (unsigned)chunks);
+  hipLaunchKernelGGL((ttm_tile_f64<KC, double>), grid, dim3(256), lds, st, in, F, out, A, L, B,
+                     K, na, nb, nbt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Largest L the TTM kernels accept (factor slice of at least one K-group in LDS).
+int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }
+
+hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
+                      const void* F, int64_t K, void* out, hipStream_t st) {
+  if (A * B == 0 || K == 0) return hipSuccess;
+  if (compute == TK_C_FP64) {
+    const int Li = (int)L;
+    const int kc_cap = std::max(1, (kLdsBudget - 8 * kF64LC * 256) / (8 * Li));
+    if (K <= 8 || kc_cap < 16)
+      return launch_f64_kc<8>((const double*)in, A, Li, B, (const double*)F, (int)K,
+                              (double*)out, st);
+    if (K <= 16 || kc_cap < 32)
+      return launch_f64_kc<16>((const double*)in, A, Li, B, (const double*)F, (int)K,
+                               (double*)out, st);
+    return launch_f64_kc<32>((const double*)in, A, Li, B, (const double*)F, (int)K,
+                             (double*)out, st);
+  }
+  if (in_dtype == TK_F32)
+    return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
+                             (float*)out, st);
+  return launch_f32<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
+                              (float*)out, st);
+}
+
+}  // namespace tk

@@ -1,0 +1,164 @@
+"""Kernel-level parity on the GPU: TTM node, Gram and FP64 eigensolver against
+the FP64 oracle, called through the C ABI.
+
+Tolerances: FP64 results within 1e-10 normwise relative; FP32 results within
+1e-5 (FP32 rounding of an L-term dot product is about sqrt(L) * 6e-8 relative);
+Gram from FP32/BF16 inputs is formed from exact FP64 products, so 1e-12."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hooi as O
+from tests.gpu_util import rel_err, subspace_dist, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+tk = pytest.importorskip("paper_1707_05594_amd")
+
+# (A, L, B, K) covering: B % 4 == 0 wide path with a ragged tail, B = 1, odd B,
+# small B, A = 1, K = 1, K = L, K not a multiple of 4, K above one LDS chunk.
+TTM_CASES = [
+    (3, 37, 1000, 5),
+    (1, 64, 4096, 20),
+    (1000, 50, 1, 7),
+    (37, 29, 7, 3),
+    (64, 33, 12, 16),
+    (5, 17, 20, 1),
+    (4, 16, 64, 16),
+    (2, 200, 200, 20),
+    (9, 23, 40, 23),
+    (3, 129, 33, 70),
+    (777, 10, 1, 10),
+]
+
+
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES)
+def test_ttm_fp32(A, L, B, K):
+    torch, dev = torch_dev()
+    print(f"ttm fp32 A={A} L={L} B={B} K={K}", flush=True)
+    g = np.random.default_rng(A * 1000 + L * 10 + K)
+    X = g.standard_normal((A, L, B)).astype(np.float32)
+    F = g.standard_normal((L, K)).astype(np.float32)
+    out = torch.full((A, K, B), float("nan"), dtype=torch.float32, device=dev)
+    tk.ttm(to_dev(X), A, L, B, to_dev(F), K, out)
+    torch.cuda.synchronize()
+    ref = O.ttm(X.astype(np.float64), F.astype(np.float64).T, 1)
+    assert rel_err(out.cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6])
+def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
+    torch, dev = torch_dev()
+    print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
+    g = np.random.default_rng(7 + A + L + B + K)
+    X = g.standard_normal((A, L, B)).astype(np.float32)
+    Xb = synth.round_to_bf16_bits(X)
+    F = g.standard_normal((L, K)).astype(np.float32)
+    xt = torch.from_numpy(Xb.view(np.int16)).view(torch.bfloat16).to(dev)
+    out = torch.empty((A, K, B), dtype=torch.float32, device=dev)
+    tk.ttm(xt, A, L, B, to_dev(F), K, out)
+    torch.cuda.synchronize()
+    ref = O.ttm(O.as_f64(Xb, "bf16"), F.astype(np.float64).T, 1)
+    assert rel_err(out.cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("A,L,B,K", [(3, 37, 100, 5), (100, 64, 1, 8), (7, 20, 9, 20),
+                                     (2, 64, 64, 33)])
+def test_ttm_fp64(A, L, B, K):
+    torch, dev = torch_dev()
+    print(f"ttm fp64 A={A} L={L} B={B} K={K}", flush=True)
+    g = np.random.default_rng(11 + A + K)
+    X = g.standard_normal((A, L, B))
+    F = g.standard_normal((L, K))
+    out = torch.empty((A, K, B), dtype=torch.float64, device=dev)
+    tk.ttm(to_dev(X), A, L, B, to_dev(F), K, out, compute="fp64")
+    torch.cuda.synchronize()
+    assert rel_err(out.cpu().numpy(), O.ttm(X, F.T, 1)) < 1e-13
+
+
+def test_ttm_identity_factor_copies_input():
+    torch, dev = torch_dev()
+    g = np.random.default_rng(5)
+    X = g.standard_normal((6, 12, 8)).astype(np.float32)
+    out = torch.empty((6, 12, 8), dtype=torch.float32, device=dev)
+    tk.ttm(to_dev(X), 6, 12, 8, to_dev(np.eye(12, dtype=np.float32)), 12, out)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), X)
+
+
+@pytest.mark.parametrize("A,L,B,dtype", [(1, 200, 8000, "f32"), (400, 200, 20, "f32"),
+                                         (8000, 200, 1, "f32"), (3, 70, 13, "f64"),
+                                         (16, 130, 16, "f32"), (5, 64, 33, "bf16")])
+def test_gram(A, L, B, dtype):
+    torch, dev = torch_dev()
+    print(f"gram A={A} L={L} B={B} {dtype}", flush=True)
+    g = np.random.default_rng(A + L + B)
+    Y = g.standard_normal((A, L, B))
+    if dtype == "f32":
+        Yd = to_dev(Y.astype(np.float32))
+        Y64 = Y.astype(np.float32).astype(np.float64)
+    elif dtype == "bf16":
+        bits = synth.round_to_bf16_bits(Y.astype(np.float32))
+        Yd = torch.from_numpy(bits.view(np.int16)).view(torch.bfloat16).to(dev)
+        Y64 = O.as_f64(bits, "bf16")
+    else:
+        Yd = to_dev(Y)
+        Y64 = Y
+    S = torch.empty((L, L), dtype=torch.float64, device=dev)
+    tk.gram(Yd, A, L, B, S)
+    torch.cuda.synchronize()
+    Sh = S.cpu().numpy()
+    assert rel_err(Sh, O.gram(Y64, 1)) < 1e-12
+    np.testing.assert_array_equal(Sh, Sh.T)
+    # deterministic: a second run gives identical bits
+    S2 = torch.empty_like(S)
+    tk.gram(Yd, A, L, B, S2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(S2.cpu().numpy(), Sh)
+
+
+def _spd_with_gap(g, L, K, gap=1e6):
+    Q, _ = np.linalg.qr(g.standard_normal((L, L)))
+    w = np.concatenate([np.sort(g.uniform(1.0, 3.0, K))[::-1] * gap,
+                        np.sort(g.uniform(0.0, 1.0, L - K))[::-1]])
+    return (Q * w) @ Q.T
+
+
+@pytest.mark.parametrize("L,K,warm", [(40, 5, False), (64, 8, False), (200, 20, False),
+                                      (200, 20, True), (80, 10, True), (128, 16, False),
+                                      (33, 33, False), (7, 1, False)])
+def test_eig_leading(L, K, warm):
+    torch, dev = torch_dev()
+    print(f"eig L={L} K={K} warm={warm}", flush=True)
+    g = np.random.default_rng(L * 3 + K)
+    S = np.stack([_spd_with_gap(g, L, K) for _ in range(3)])
+    V0 = None
+    if warm:
+        V0 = np.stack([np.linalg.qr(O.leading_eigvecs(s, K)[0] +
+                                    1e-3 * g.standard_normal((L, K)))[0] for s in S])
+    F, ev = tk.eig_leading(to_dev(S), K, V0=to_dev(V0) if V0 is not None else None)
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    ev = ev.cpu().numpy()
+    for m in range(3):
+        Fr, wr = O.leading_eigvecs(S[m], K)
+        np.testing.assert_allclose(ev[m], wr, rtol=1e-12)
+        nS = np.linalg.norm(S[m], 2)
+        assert np.linalg.norm(S[m] @ F[m] - F[m] * ev[m]) <= 1e-11 * nS
+        assert np.linalg.norm(F[m].T @ F[m] - np.eye(K)) <= 1e-13
+        assert subspace_dist(F[m], Fr) < 1e-10
+        # eigenvalues are distinct: the sign rule makes the vectors unique
+        assert np.abs(F[m] - Fr).max() < 1e-9
+
+
+def test_eig_full_jacobi_random_small():
+    # L <= 48 runs a full Jacobi: no gap needed
+    torch, dev = torch_dev()
+    g = np.random.default_rng(3)
+    M = g.standard_normal((2, 30, 30))
+    S = np.einsum("mij,mkj->mik", M, M)
+    F, ev = tk.eig_leading(to_dev(S), 30)
+    torch.cuda.synchronize()
+    for m in range(2):
+        w = np.linalg.eigvalsh(S[m])[::-1]
+        np.testing.assert_allclose(ev.cpu().numpy()[m], w, rtol=1e-11, atol=1e-11 * w[0])
