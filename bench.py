@@ -1,0 +1,185 @@
+"""Benchmark: HOOI iterations/s on one MI355X for the dense Tucker hot path.
+
+Workload: planted 200x200x200x200 FP32 tensor, Tucker rank 20 per mode, 1e-3
+relative Gaussian noise, HOSVD start, DP-optimal TTM-tree.  One step is one
+HOOI invocation (every TTM of the tree, the Grams, the FP64 eigensolver and
+the folded core + error); the timed region is hooi_iterate(steps), whose final
+direct core chain (the error of the last step) is included.
+
+Prints ONE JSON line.  Extra objects:
+  roofline     -- the dominant kernel (the root-level TTMs that read T), timed
+                  with HIP events on the library's stream; algorithmic bytes
+                  = 4 * (|In| + |Out|) + factor per launch, HBM peak 8 TB/s.
+  cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
+                  host for a bounded sample: one HOOI invocation of the same
+                  tensor.
+  mixed        -- the same HOOI with T stored as BF16 (FP32 MFMA compute),
+                  reported beside the FP32 run at its relative error.
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "HOOI iters/sec + TTM GFLOP/s (% MFMA peak), mixed vs FP32 at equal rel. error"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+WORKLOAD = "planted_200x200x200x200_r20_f32"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def root_ttm_roofline(ctx, plan, reps=3):
+    """Average duration of the root-level TTM launches (HIP events, ctx stream)."""
+    nodes = plan.nodes()
+    roots = [i for i, n in enumerate(nodes) if n["parent"] < 0 and not n["is_leaf"]]
+    times = []
+    for _ in range(reps):
+        ms = ctx.profile_tree()
+        times.extend(ms[i] for i in roots)
+    avg_ms = sum(times) / len(times)
+    L, K = plan.L, plan.K
+    per_launch = []
+    for i in roots:
+        n = nodes[i]
+        per_launch.append(4 * (n["in_card"] + n["out_card"]) + 4 * L[n["mode"]] * K[n["mode"]])
+    bytes_per_launch = sum(per_launch) / len(per_launch)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="ttm_wide_f32 (root nodes, reads T)", launches=len(times),
+                avg_ms=round(avg_ms, 4), bytes_per_launch=int(bytes_per_launch)), ms
+
+
+def cpu_baseline(T32, K, F0):
+    """Oracle (FP64 NumPy, naive chains) on one HOOI invocation of the same tensor."""
+    import numpy as np
+    from oracle import hooi as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    T64 = T32.astype(np.float64)
+    t0 = time.perf_counter()
+    O.hooi_step(T64, F0, K)
+    dt = time.perf_counter() - t0
+    del T64
+    return dict(value=round(1.0 / dt, 5), unit="HOOI iters/s", cores=int(threads), kind="oracle",
+                sample="one FP64 HOOI invocation (naive per-mode TTM chains + eigh + core) of "
+                       "the same 200^4 rank-20 tensor, from the GPU's HOSVD factors",
+                seconds=round(dt, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding is described in DESIGN.md only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1707_05594_amd as tk
+    import synth
+
+    t0 = time.perf_counter()
+    T, info = synth.workload(WORKLOAD)
+    L, K = info["L"], info["K"]
+    log(f"generated {WORKLOAD} in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    Td = torch.from_numpy(T).to(dev)
+    torch.cuda.synchronize()
+    plan = tk.ttm_tree_plan(L, K)
+    ctx = tk.hooi_init(Td, K, plan=plan, compute="fp32")
+    F0 = ctx.factors()
+    log(f"plan {plan.string()} macs {plan.cost()}")
+
+    if args.warmup > 0:
+        ctx.iterate(args.warmup)
+    ctx.set_factors(F0)  # timed run starts from the HOSVD factors again
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    errs = ctx.iterate(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    ms_per_step = 1e3 * elapsed / args.steps
+    its = args.steps / elapsed
+    log(f"{args.steps} steps in {elapsed * 1e3:.2f} ms, errors {errs}")
+    log(f"eigensolver steps per mode (last update): {ctx.eig_iterations()}")
+
+    roof, node_ms = root_ttm_roofline(ctx, plan)
+    tree_ms = sum(node_ms)
+    tree_macs = plan.cost()
+    gflops_step = 2.0 * tree_macs / (ms_per_step * 1e-3) / 1e9
+    gflops_tree = 2.0 * tree_macs / (tree_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(its, 3),
+        "unit": "HOOI iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "planted 200x200x200x200 FP32, Tucker rank 20/mode, 1e-3 rel "
+                               "noise, HOSVD start, DP-optimal TTM-tree",
+                   "L": list(L), "K": list(K), "tree": plan.string(), "tree_macs": tree_macs},
+        "ttm_gflops": round(gflops_step, 1),
+        "ttm_gflops_tree_only": round(gflops_tree, 1),
+        "ttm_frac_fp32_mfma_peak": round(gflops_step / (FP32_MFMA_PEAK_TFLOPS * 1e3), 4),
+        "rel_err": errs[-1],
+        "roofline": roof,
+    }
+
+    if not args.skip_mixed:
+        Tb = Td.to(torch.bfloat16)
+        ctxb = tk.hooi_init(Tb, K, plan=plan, compute="fp32", F0=F0)
+        ctxb.iterate(max(1, args.warmup))
+        ctxb.set_factors(F0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        errs_b = ctxb.iterate(args.steps)
+        torch.cuda.synchronize()
+        eb = time.perf_counter() - t2
+        # error of the BF16-derived decomposition against the original FP32 tensor
+        ctx.set_factors(ctxb.factors())
+        err_vs_f32 = ctx.error()[0]
+        out["mixed"] = {"storage": "bf16 T", "compute": "fp32 MFMA, FP64 eigensolver",
+                        "value": round(args.steps / eb, 3), "unit": "HOOI iters/s",
+                        "ms_per_step": round(1e3 * eb / args.steps, 4),
+                        "speedup_vs_fp32": round((args.steps / eb) / its, 3),
+                        "rel_err_vs_fp32_T": err_vs_f32, "rel_err_fp32_run": errs[-1],
+                        "rel_err_vs_bf16_T": errs_b[-1]}
+        del ctxb, Tb
+        log(f"mixed bf16 storage: {out['mixed']['value']} it/s err {errs_b[-1]}")
+
+    if not args.skip_cpu_baseline:
+        log("timing the FP64 oracle on one HOOI invocation ...")
+        out["cpu_baseline"] = cpu_baseline(T, K, F0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -166,6 +166,10 @@ int tk_get_gram(tk_ctx* ctx, int n, double* host);
  * factors; ms_out has one entry per plan node (leaves: Gram time). */
 int tk_profile_tree(tk_ctx* ctx, float* ms_out, int cap, int* n);
 
+/* Subspace steps the FP64 eigensolver used for each mode in the most recent
+ * factor update (out: N ints, host).  Observability aid. */
+int tk_eig_iterations(tk_ctx* ctx, int* out);
+
 void hooi_free(tk_ctx* ctx);
 
 /* ---- kernel-level entry points (device pointers, enqueued on `stream`) ---- */

@@ -71,6 +71,7 @@ _SIGS = {
     "tk_get_leaf": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tk_get_gram": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tk_profile_tree": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int, _ip], ctypes.c_int),
+    "tk_eig_iterations": ([_vp, _ip], ctypes.c_int),
     "hooi_free": ([_vp], None),
     "tk_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp],
                ctypes.c_int),
@@ -285,6 +286,11 @@ class Context:
         out = np.empty((self.L[n], self.L[n]), dtype=np.float64)
         _check(lib().tk_get_gram(self._h, n, out.ctypes.data_as(_dp)))
         return out
+
+    def eig_iterations(self):
+        arr = (ctypes.c_int * self.N)()
+        _check(lib().tk_eig_iterations(self._h, arr))
+        return list(arr)
 
     def profile_tree(self):
         n = ctypes.c_int()

@@ -38,17 +38,29 @@ struct Elem<uint16_t> {
   __device__ __forceinline__ static double to_f64(uint16_t v) { return (double)bf16_to_f32(v); }
 };
 
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+
 // Four consecutive elements starting at a 4-element-aligned index, as FP32.
+// NT: non-temporal (streaming) load, for data read once.
+template <bool NT = false>
 __device__ __forceinline__ f4 load4_f32(const float* p) {
-  return *reinterpret_cast<const f4*>(p);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+  else
+    return *reinterpret_cast<const f4*>(p);
 }
+template <bool NT = false>
 __device__ __forceinline__ f4 load4_f32(const uint16_t* p) {
-  uint2 v = *reinterpret_cast<const uint2*>(p);
+  u2v v;
+  if constexpr (NT)
+    v = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+  else
+    v = *reinterpret_cast<const u2v*>(p);
   f4 r;
-  r[0] = __uint_as_float(v.x << 16);
-  r[1] = __uint_as_float(v.x & 0xFFFF0000u);
-  r[2] = __uint_as_float(v.y << 16);
-  r[3] = __uint_as_float(v.y & 0xFFFF0000u);
+  r[0] = __uint_as_float(v[0] << 16);
+  r[1] = __uint_as_float(v[0] & 0xFFFF0000u);
+  r[2] = __uint_as_float(v[1] << 16);
+  r[3] = __uint_as_float(v[1] & 0xFFFF0000u);
   return r;
 }
 

@@ -111,16 +111,28 @@ struct tk_ctx {
   double normT2 = 0.0;
   double normG2 = 0.0;
   bool core_valid = false;
-  int maxit_warm = 30, maxit_cold = 200;
+  int maxit_warm = 20, maxit_cold = 100;
   double eig_tol = 1e-11;
+  int Lmax = 0, pmax = 0;
+
+  // Side stream for the per-leaf eigensolves (default priority), joined back
+  // into `st` with events at the end of every tree pass.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_leaf[TK_MAX_MODES] = {};
+  hipEvent_t ev_join = nullptr;
 
   ~tk_ctx() {
+    if (side) (void)hipStreamSynchronize(side);
     void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc, S, ev, eigwork, status, jobs,
                     jobs_cold, gpart, rpart, scal, core};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     for (void* p : leaves)
       if (p) (void)hipFree(p);
+    for (hipEvent_t e : ev_leaf)
+      if (e) (void)hipEventDestroy(e);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
   }
 
   const void* fc(int n) const {
@@ -132,8 +144,9 @@ struct tk_ctx {
 namespace {
 
 int run_eig(tk_ctx* c, bool warm, double* F_out, int maxit) {
-  TK_HIP(launch_eig(c->s.N, warm ? c->jobs : c->jobs_cold, c->S, c->F64a, F_out, c->ev,
-                    c->eigwork, c->status, maxit, c->eig_tol, c->st));
+  TK_HIP(launch_eig(c->s.N, warm ? c->jobs : c->jobs_cold, 0, c->Lmax, c->pmax, c->S, c->F64a,
+                    F_out, c->ev, c->eigwork, c->status, c->status + c->s.N, maxit, c->eig_tol,
+                    c->st));
   return TK_OK;
 }
 
@@ -159,7 +172,10 @@ int check_status(tk_ctx* c) {
 //   fold_dst >= 0: fold the core (G = Y_m x_m F_m^T) and store ||G||^2 in scal[fold_dst].
 //   keep: copy every leaf tensor to c->leaves.
 //   ev_t: optional per-node timing events (2 per node).
-int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t) {
+//   eig_out: if set, every leaf's warm-started eigensolve (-> eig_out) runs on
+//   the side stream as soon as its Gram is formed, overlapping the rest of the
+//   tree; the pass ends by joining the side stream into c->st.
+int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, double* eig_out = nullptr) {
   const Shape& s = c->s;
   const auto& nodes = c->tree.nodes;
   for (size_t u = 0; u < nodes.size(); ++u) {
@@ -170,14 +186,22 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t) {
     view(s, nd.pre_mask, nd.mode, &A, &L, &B);
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
     if (!nd.is_leaf) {
+      // children of the root stream T (too large to stay in cache between them)
       TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
-                        c->wsp(c->node_off[u]), c->st));
+                        c->wsp(c->node_off[u]), c->st, nd.parent < 0));
     } else {
       const int n = nd.mode;
       TK_HIP(launch_gram(in_dt, in, A, L, B, c->S + c->sofs[n], c->gpart, c->st));
       if (keep)
         TK_HIP(hipMemcpyAsync(c->leaves[n], in, (size_t)c->leaf_elems[n] * dtype_size(in_dt),
                               hipMemcpyDeviceToDevice, c->st));
+      if (eig_out) {
+        TK_HIP(hipEventRecord(c->ev_leaf[n], c->st));
+        TK_HIP(hipStreamWaitEvent(c->side, c->ev_leaf[n], 0));
+        const EigJob& j = c->jobs_h[n];
+        TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, eig_out, c->ev, c->eigwork,
+                          c->status, c->status + s.N, c->maxit_warm, c->eig_tol, c->side));
+      }
       if (fold_dst >= 0 && n == c->fold_leaf) {
         TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
         TK_HIP(launch_sumsq(c->wdtype, c->core, c->core_elems, c->rpart, c->scal + fold_dst,
@@ -185,6 +209,10 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t) {
       }
     }
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u + 1], c->st));
+  }
+  if (eig_out) {
+    TK_HIP(hipEventRecord(c->ev_join, c->side));
+    TK_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
   }
   return TK_OK;
 }
@@ -201,7 +229,7 @@ int core_chain(tk_ctx* c, int dst) {
     int64_t A, L, B;
     view(s, pre, n, &A, &L, &B);
     void* out = (i == N - 1) ? c->core : c->wsp((i % 2 == 0) ? 0 : c->chain_a);
-    TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], out, c->st));
+    TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], out, c->st, i == 0));
     pre |= 1u << n;
     in = out;
     in_dt = c->wdtype;
@@ -333,8 +361,20 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     j.ev_off = (int64_t)c->kofs[n];
     j.work_off = (int64_t)work;
     work += (size_t)2 * j.L * j.p;
+    c->Lmax = std::max(c->Lmax, j.L);
+    c->pmax = std::max(c->pmax, j.p);
   }
   std::vector<EigJob> cold = c->jobs_h;
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    for (int n = 0; n < N && e == hipSuccess; ++n)
+      e = hipEventCreateWithFlags(&c->ev_leaf[n], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(TK_EDEVICE, "stream/event creation failed: %s", hipGetErrorString(e));
+    }
+  }
   for (auto& j : cold) j.V0_off = -1;
 
   // ---- Gram workspace: leaves and the HOSVD unfoldings of T
@@ -357,7 +397,7 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   if ((rc = dalloc((void**)&c->S, sizeof(double) * c->sofs[N]))) return bail(rc);
   if ((rc = dalloc((void**)&c->ev, sizeof(double) * c->kofs[N]))) return bail(rc);
   if ((rc = dalloc((void**)&c->eigwork, sizeof(double) * work))) return bail(rc);
-  if ((rc = dalloc((void**)&c->status, sizeof(int) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->status, sizeof(int) * 2 * N))) return bail(rc);
   if ((rc = dalloc((void**)&c->jobs, sizeof(EigJob) * N))) return bail(rc);
   if ((rc = dalloc((void**)&c->jobs_cold, sizeof(EigJob) * N))) return bail(rc);
   if ((rc = dalloc((void**)&c->gpart, sizeof(double) * c->gpart_elems))) return bail(rc);
@@ -439,8 +479,7 @@ extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
   // scal[0] = ||T||^2 (kept), scal[1 + t] = ||G^(t)||^2, t = 0..iters
   TK_HIP(launch_fill_int(c->status, c->s.N, 0, c->st));
   for (int t = 0; t < iters; ++t) {
-    if (int rc = tree_pass(c, 1 + t, false, nullptr)) return rc;
-    if (int rc = run_eig(c, true, c->F64b, c->maxit_warm)) return rc;
+    if (int rc = tree_pass(c, 1 + t, false, nullptr, c->F64b)) return rc;
     std::swap(c->F64a, c->F64b);
     if (c->wdtype == TK_F64) c->Fc = c->F64a;
     if (int rc = refresh_compute_factors(c)) return rc;
@@ -667,6 +706,15 @@ extern "C" int tk_profile_tree(tk_ctx* c, float* ms_out, int cap, int* n) {
   return rc;
 }
 
+extern "C" int tk_eig_iterations(tk_ctx* c, int* out) {
+  clear_error();
+  if (!c || !out) return fail(TK_EINVAL, "null argument");
+  TK_HIP(hipMemcpyAsync(out, c->status + c->s.N, sizeof(int) * c->s.N, hipMemcpyDeviceToHost,
+                        c->st));
+  TK_HIP(hipStreamSynchronize(c->st));
+  return TK_OK;
+}
+
 extern "C" void hooi_free(tk_ctx* c) { delete c; }
 
 // ---------------------------------------------------------------- kernel-level entry points --
@@ -743,7 +791,9 @@ extern "C" int tk_eig_leading(int count, int L, int K, const double* S, const do
   std::vector<int> sth(count, 0);
   hipError_t e = hipMemcpyAsync(jd, jobs.data(), sizeof(EigJob) * count, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_fill_int(status, count, 0, st);
-  if (e == hipSuccess) e = launch_eig(count, jd, S, V0, F, evals, work, status, V0 ? 30 : 200, 1e-11, st);
+  if (e == hipSuccess)
+    e = launch_eig(count, jd, 0, L, p, S, V0, F, evals, work, status, nullptr, V0 ? 20 : 100,
+                   1e-11, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sth.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

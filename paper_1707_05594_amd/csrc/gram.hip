@@ -37,29 +37,44 @@ template <typename TIn>
 __device__ __forceinline__ void gram_load_tile(double (*X)[kGT], const TIn* __restrict__ Y,
                                                int L, int64_t B, int row0, int64_t cs,
                                                int64_t cend) {
+  // kGC * kGT / 256 = 8 elements per thread, all loads issued before the stores
   const int tid = threadIdx.x;
+  constexpr int kPer = kGC * kGT / 256;
+  double v[kPer];
   if (B == 1) {
     // Y[a, l]: rows of one column are contiguous -> threads walk rows fastest
-    for (int e = tid; e < kGC * kGT; e += 256) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
       const int rr = e % kGT, cc = e / kGT;
       const int64_t c = cs + cc;
       const int row = row0 + rr;
-      double v = 0.0;
-      if (c < cend && row < L) v = Elem<TIn>::to_f64(Y[c * L + row]);
-      X[cc][rr] = v;
+      v[u] = (c < cend && row < L) ? Elem<TIn>::to_f64(Y[c * L + row]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      X[e / kGT][e % kGT] = v[u];
     }
   } else {
-    for (int e = tid; e < kGC * kGT; e += 256) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
       const int cc = e % kGC, rr = e / kGC;
       const int64_t c = cs + cc;
       const int row = row0 + rr;
-      double v = 0.0;
+      double x = 0.0;
       if (c < cend && row < L) {
         const int64_t a = c / B;
         const int64_t b = c - a * B;
-        v = Elem<TIn>::to_f64(Y[(a * L + row) * B + b]);
+        x = Elem<TIn>::to_f64(Y[(a * L + row) * B + b]);
       }
-      X[cc][rr] = v;
+      v[u] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      X[e % kGC][e / kGC] = v[u];
     }
   }
 }
@@ -135,9 +150,9 @@ GramGeom gram_geom(int64_t L, int64_t C) {
   GramGeom g;
   g.T = (int)((L + kGT - 1) / kGT);
   g.npairs = g.T * (g.T + 1) / 2;
-  const int64_t target = std::max<int64_t>(1, 2048 / g.npairs);
+  const int64_t target = std::max<int64_t>(1, 4096 / g.npairs);
   int64_t cc = (C + target - 1) / target;
-  cc = std::max<int64_t>(cc, 512);
+  cc = std::max<int64_t>(cc, 128);
   cc = (cc + kGC - 1) / kGC * kGC;
   g.cchunk = cc;
   g.nchunks = (C + cc - 1) / cc;

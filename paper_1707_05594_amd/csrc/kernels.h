@@ -8,8 +8,10 @@
 namespace tk {
 
 // TTM node: Out[a,k,b] = sum_l F[l,k] In[a,l,b]  (ttm.hip)
+// stream_in: the input is read once (streamed past the caches)
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
-                      const void* F, int64_t K, void* out, hipStream_t st);
+                      const void* F, int64_t K, void* out, hipStream_t st,
+                      bool stream_in = false);
 int ttm_max_L();
 
 // Gram S = Y_(n) Y_(n)^T (gram.hip); `part` holds gram_workspace_elems(L, A*B) doubles
@@ -24,9 +26,13 @@ struct EigJob {
   int L, K, p, pad_;
   int64_t S_off, V0_off, F_off, ev_off, work_off;
 };
-hipError_t launch_eig(int count, const EigJob* jobs_dev, const double* S_base,
-                      const double* V0_base, double* F_base, double* ev_base, double* work_base,
-                      int* status, int maxit, double tol, hipStream_t st);
+// Jobs [job0, job0 + count) of the device table; Lmax / pmax bound their L and p.
+// status[job] is set on failure only (1: no convergence, 2: non-finite);
+// iters (nullable) receives the subspace steps each job used.
+hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int pmax,
+                      const double* S_base, const double* V0_base, double* F_base,
+                      double* ev_base, double* work_base, int* status, int* iters, int maxit,
+                      double tol, hipStream_t st);
 int eig_block_size(int L, int K, int64_t rank_bound);
 int eig_max_K();
 

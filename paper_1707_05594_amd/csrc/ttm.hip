@@ -55,8 +55,9 @@ __device__ __forceinline__ void stage_factor(float* FT, const float* __restrict_
 // ------------------------------------------------------------------ wide path --
 // Requires B % 4 == 0.  A wave owns 256 consecutive columns; lane i owns
 // columns c0 + 4i .. c0 + 4i + 3 (same a, consecutive b).  grid.y splits K
-// into chunks of 4*KG rows.
-template <int KG, typename TIn>
+// into chunks of 4*KG rows.  NT: the input is streamed (read once, e.g. T at
+// the root), so its loads bypass cache retention.
+template <int KG, typename TIn, bool NT>
 __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
                                                     const float* __restrict__ F,
                                                     float* __restrict__ out, int64_t C, int L,
@@ -81,13 +82,13 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  constexpr int U = 4;
+  constexpr int U = 8;
   int l = 0;
   for (; l + U <= L; l += U) {
     f4 x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      x[u] = active ? load4_f32(p + (int64_t)(l + u) * B) : f4{0.f, 0.f, 0.f, 0.f};
+      x[u] = active ? load4_f32<NT>(p + (int64_t)(l + u) * B) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
     }
   }
   for (; l < L; ++l) {
-    const f4 x = active ? load4_f32(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
+    const f4 x = active ? load4_f32<NT>(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
       const float fa = ft[l * KG + g];
@@ -118,6 +119,67 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
         f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
         *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
       }
+    }
+}
+
+// ------------------------------------------------------------------- row path --
+// B == 1 (the last mode): Out[a, k] = sum_l In[a, l] F[l, k], rows of In
+// contiguous.  Requires L % 4 == 0.  Lane i owns row a = 256*block + thread and
+// walks it with 16-byte loads (eight in flight: one 128-byte line of FP32);
+// each load feeds four MFMAs, one per l.  In a 4x4x1 MFMA the B operand of
+// lane i is its own row value, the A operands (four k's of row l of F) are
+// the same for every block, so lane i accumulates four k's of its own row.
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t A, int L,
+                                                    int Kt) {
+  extern __shared__ float smem[];
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wave_row0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+  if (wave_row0 >= A) return;  // whole wave idle
+  const int64_t a = wave_row0 + lane;
+  const bool active = a < A;
+  const TIn* p = in + (active ? a : 0) * L;
+  const float* ft = smem + (lane & 3) * L * KG;
+
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int U = 8;
+  int l = 0;
+  for (; l + 4 * U <= L; l += 4 * U) {
+    f4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = active ? load4_f32<NT>(p + l + 4 * u) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+          acc[g] = mfma4x4x1(ft[(l + 4 * u + j) * KG + g], x[u][j], acc[g]);
+  }
+  for (; l < L; l += 4) {
+    const f4 x = active ? load4_f32<NT>(p + l) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l + j) * KG + g], x[j], acc[g]);
+  }
+  if (!active) return;
+  float* q = out + a * Kt;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) q[k] = acc[g][m];
     }
 }
 
@@ -160,13 +222,26 @@ __global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
     const int lc = min(kTileLC, L - l0);
     __syncthreads();
     const int total = nav * lc * nbv;
-    for (int e = threadIdx.x; e < total; e += 256) {
-      const int bb = e % nbv;
-      const int t = e / nbv;
-      const int ll = t % lc;
-      const int aa = t / lc;
-      X[ll * 256 + aa * nb + bb] =
-          Elem<TIn>::to_f32(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+    // eight loads in flight per thread before the LDS stores
+    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {
+      float v[8];
+      int dst[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256;
+        dst[u] = -1;
+        if (e < total) {
+          const int bb = e % nbv;
+          const int t = e / nbv;
+          const int ll = t % lc;
+          const int aa = t / lc;
+          dst[u] = ll * 256 + aa * nb + bb;
+          v[u] = Elem<TIn>::to_f32(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (dst[u] >= 0) X[dst[u]] = v[u];
     }
     __syncthreads();
     for (int ll = 0; ll < lc; ++ll) {
@@ -251,17 +326,30 @@ namespace {
 
 constexpr int kLdsBudget = 64 * 1024;
 
-template <typename TIn, int KG>
-hipError_t launch_f32_kg(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
-                         float* out, hipStream_t st) {
+enum class Path { kWide, kRows, kTile };
+
+template <typename TIn>
+Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
+  const bool in_al = (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+  if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) return Path::kWide;
+  if (B == 1 && L % 4 == 0 && in_al) return Path::kRows;
+  return Path::kTile;
+}
+
+template <typename TIn, int KG, bool NT>
+hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
+                         int K, float* out, hipStream_t st) {
   const int chunks = (K + 4 * KG - 1) / (4 * KG);
-  const int64_t C = A * B;
-  const bool aligned = ((uintptr_t)in % (4 * sizeof(TIn)) == 0) && ((uintptr_t)out % 16 == 0);
-  if (B % 4 == 0 && B >= 16 && aligned) {
+  if (path == Path::kWide) {
+    const int64_t C = A * B;
     const size_t lds = (size_t)16 * L * KG;
-    const int64_t blocks = (C + 1023) / 1024;
-    dim3 grid((unsigned)blocks, (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_wide_f32<KG, TIn>), grid, dim3(256), lds, st, in, F, out, C, L, B,
+    dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, C, L, B,
+                       K);
+  } else if (path == Path::kRows) {
+    const size_t lds = (size_t)16 * L * KG;
+    dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, A, L,
                        K);
   } else {
     const int nb = (int)std::min<int64_t>(B, 256);
@@ -276,12 +364,30 @@ hipError_t launch_f32_kg(const TIn* in, int64_t A, int L, int64_t B, const float
   return hipGetLastError();
 }
 
+template <typename TIn, bool NT>
+hipError_t launch_f32_nt(Path path, int kg, const TIn* in, int64_t A, int L, int64_t B,
+                         const float* F, int K, float* out, hipStream_t st) {
+  switch (kg) {
+    case 1: return launch_f32_kg<TIn, 1, NT>(path, in, A, L, B, F, K, out, st);
+    case 2: return launch_f32_kg<TIn, 2, NT>(path, in, A, L, B, F, K, out, st);
+    case 3: return launch_f32_kg<TIn, 3, NT>(path, in, A, L, B, F, K, out, st);
+    case 4: return launch_f32_kg<TIn, 4, NT>(path, in, A, L, B, F, K, out, st);
+    case 5: return launch_f32_kg<TIn, 5, NT>(path, in, A, L, B, F, K, out, st);
+    case 6: return launch_f32_kg<TIn, 6, NT>(path, in, A, L, B, F, K, out, st);
+    case 8: return launch_f32_kg<TIn, 8, NT>(path, in, A, L, B, F, K, out, st);
+    case 12: return launch_f32_kg<TIn, 12, NT>(path, in, A, L, B, F, K, out, st);
+    default: return launch_f32_kg<TIn, 16, NT>(path, in, A, L, B, F, K, out, st);
+  }
+}
+
 template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
-                      float* out, hipStream_t st) {
+                      float* out, bool stream_in, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path):
   // the smallest instance covering ceil(K/4) groups if it fits, else the
-  // largest that fits (K is then covered by several chunks).
+  // largest that fits (K is then covered by several chunks).  Small grids
+  // trade a larger KG for more K-chunks (more blocks; the input is re-read
+  // from cache).
   static const int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
   const int need = (K + 3) / 4;
   const int kg_cap = std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L));
@@ -293,17 +399,29 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
       kg = c;
       break;
     }
-  switch (kg) {
-    case 1: return launch_f32_kg<TIn, 1>(in, A, L, B, F, K, out, st);
-    case 2: return launch_f32_kg<TIn, 2>(in, A, L, B, F, K, out, st);
-    case 3: return launch_f32_kg<TIn, 3>(in, A, L, B, F, K, out, st);
-    case 4: return launch_f32_kg<TIn, 4>(in, A, L, B, F, K, out, st);
-    case 5: return launch_f32_kg<TIn, 5>(in, A, L, B, F, K, out, st);
-    case 6: return launch_f32_kg<TIn, 6>(in, A, L, B, F, K, out, st);
-    case 8: return launch_f32_kg<TIn, 8>(in, A, L, B, F, K, out, st);
-    case 12: return launch_f32_kg<TIn, 12>(in, A, L, B, F, K, out, st);
-    default: return launch_f32_kg<TIn, 16>(in, A, L, B, F, K, out, st);
+  const Path path = choose_path(in, out, L, B);
+  int64_t blocks = 0;
+  if (path == Path::kWide) blocks = (A * B + 1023) / 1024;
+  else if (path == Path::kRows) blocks = (A + 255) / 256;
+  if (blocks > 0 && blocks < 256 && need > 1) {
+    // fewer blocks than CUs: cut K into balanced chunks (2, 3, ... groups of
+    // ceil(need/chunks)) until the grid covers the chip
+    for (int chunks = 2; chunks <= need; ++chunks) {
+      const int want = (need + chunks - 1) / chunks;
+      int pick = 0;
+      for (int c : kInst)
+        if (c >= want && c <= kg_cap) {
+          pick = c;
+          break;
+        }
+      if (pick == 0) break;
+      kg = pick;
+      if (blocks * ((need + kg - 1) / kg) >= 256) break;
+    }
   }
+  if (stream_in)
+    return launch_f32_nt<TIn, true>(path, kg, in, A, L, B, F, K, out, st);
+  return launch_f32_nt<TIn, false>(path, kg, in, A, L, B, F, K, out, st);
 }
 
 template <int KC>
@@ -327,7 +445,7 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }
 
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
-                      const void* F, int64_t K, void* out, hipStream_t st) {
+                      const void* F, int64_t K, void* out, hipStream_t st, bool stream_in) {
   if (A * B == 0 || K == 0) return hipSuccess;
   if (compute == TK_C_FP64) {
     const int Li = (int)L;
@@ -343,9 +461,9 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   }
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
-                             (float*)out, st);
+                             (float*)out, stream_in, st);
   return launch_f32<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
-                              (float*)out, st);
+                              (float*)out, stream_in, st);
 }
 
 }  // namespace tk

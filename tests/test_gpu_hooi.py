@@ -122,9 +122,12 @@ def test_checkpoint_resume_is_exact_and_runs_are_deterministic():
     Fmid = b.factors()
     c = tk.hooi_init(Td, K, compute="fp64", F0=Fmid)
     e2 = c.iterate(2)
-    np.testing.assert_array_equal(np.array(e1 + e2), np.array(e_all))
+    # factors are bitwise identical; the error of the iterate at the resume point
+    # comes from the direct core chain instead of the folded core (another
+    # summation order), so errors agree to rounding of 1 - ||G||^2/||T||^2
     for n in range(3):
         np.testing.assert_array_equal(c.factor(n), a.factor(n))
+    np.testing.assert_allclose(np.array(e1 + e2), np.array(e_all), rtol=1e-12)
     d = tk.hooi_init(Td, K, compute="fp64")
     np.testing.assert_array_equal(np.array(d.iterate(4)), np.array(e_all))
 

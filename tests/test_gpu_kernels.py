@@ -29,6 +29,9 @@ TTM_CASES = [
     (9, 23, 40, 23),
     (3, 129, 33, 70),
     (777, 10, 1, 10),
+    (1000, 64, 1, 20),   # row path (B = 1, L % 4 == 0)
+    (257, 200, 1, 37),   # row path, K over several groups, ragged rows
+    (5, 48, 1, 3),       # row path, tiny grid
 ]
 
 
@@ -46,7 +49,7 @@ def test_ttm_fp32(A, L, B, K):
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6])
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-3:])
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
