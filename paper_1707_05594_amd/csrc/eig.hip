@@ -4,26 +4,29 @@
 // One workgroup per matrix.  Subspace iteration with Rayleigh-Ritz on a block
 // of p >= K columns:
 //
-//   V = orth(start)                     start = previous factor + fill columns
+//   V = orth(start)
 //   loop:  W = S V
-//          H = V^T W,  H = Z diag(theta) Z^T   (Jacobi, one wavefront)
+//          H = V^T W,  H = Z diag(theta) Z^T   (cyclic Jacobi)
 //          V <- V Z,  W <- W Z           (Ritz pairs, theta descending)
 //          stop when ||W_j - theta_j V_j|| <= tol * theta_0 for every j < K
 //          V = orth(W)                   (power step)
 //
-// A warm start (previous factors) runs with a small block p = K + 4; if it
-// has not converged after `maxit` steps the block grows to p_max (fresh fill
-// columns) for up to another `maxit` steps.  p = L makes the Rayleigh-Ritz
-// step a full Jacobi eigen-decomposition (used when L is small).
+// A warm start begins from the previous factors alone (p = K): the Ritz
+// matrix is then nearly diagonal and Jacobi converges in one or two sweeps.
+// If that has not converged after `maxit` steps, the block grows to p_max
+// with deterministic fill columns for up to another `maxit` steps.  A cold
+// start uses p_max from the outset; p = L makes the Rayleigh-Ritz step a full
+// Jacobi eigen-decomposition (used when L is small).
 // orth() is Cholesky-QR applied twice to column-normalised blocks; a column
 // whose normalised Cholesky pivot vanishes (rank deficiency) is zeroed.
 // Output: the first K Ritz vectors, each with its largest-magnitude entry
 // (lowest row on ties) made positive, and their eigenvalues.
 //
-// The blocks V and W live in LDS when 2 L p_max doubles fit (else in a global
-// work area); H, Z and the Jacobi double buffer always live in LDS.  The
-// products S V, V^T W, V Z use all 256 threads; Cholesky and the p x p Jacobi
-// run on wavefront 0 alone with wavefront-level ordering.
+// The kernel is instantiated for a padded block width PS (a multiple of 8,
+// PS >= p): V, W have row stride PS, H and Z are PS x PS, and every loop runs
+// over PS columns with static bounds (the columns p..PS-1 hold zeros, Z holds
+// the identity there), so loads are batched instead of serialised behind
+// guards.  V and W live in LDS when they fit, else in a global work area.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,11 +41,6 @@ namespace tk {
 constexpr int kEigPMax = 48;
 constexpr int kEigThreads = 256;
 constexpr int kEigLdsMax = 160 * 1024;
-
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __device__ __forceinline__ double hash_unit(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
@@ -60,240 +58,240 @@ struct EigSmall {
   int partner[kEigPMax];
   int perm[kEigPMax];
   int flag;
+  double minpiv;
 };
 
+template <int PS>
 struct EigMem {
-  double* H;   // p_max^2 (LDS)
-  double* Z;   // p_max^2 (LDS)
-  double* H2;  // p_max^2 (LDS)
-  double* V;   // L x p, row stride p (LDS or global)
-  double* W;
+  double* H;   // PS x PS (LDS)
+  double* Z;   // PS x PS (LDS)
+  double* H2;  // PS x PS (LDS)
+  double* V;   // L x PS (LDS or global)
+  double* W;   // L x PS
   EigSmall* sm;
 };
 
-// Sum over the block of per-thread vectors v[0..n-1] -> out[0..n-1].
-__device__ __forceinline__ void block_sum_vec(const double (&v)[kEigPMax], int n, double* red,
-                                              double* out) {
+// Sum over the block of per-thread vectors v[0..PS-1] -> out[0..PS-1].
+template <int PS>
+__device__ __forceinline__ void block_sum_vec(const double (&v)[PS], double* red, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int j = 0; j < kEigPMax; ++j) {
-    if (j < n) {
-      double s = wave_sum(v[j]);
-      if (lane == 0) red[wave * kEigPMax + j] = s;
-    }
+  for (int j = 0; j < PS; ++j) {
+    const double s = wave_sum(v[j]);
+    if (lane == 0) red[wave * kEigPMax + j] = s;
   }
   __syncthreads();
-  if (threadIdx.x < n) {
+  if (threadIdx.x < PS) {
     double s = 0.0;
+#pragma unroll
     for (int w = 0; w < 4; ++w) s += red[w * kEigPMax + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
 }
 
-// G = V^T V (p x p) with V row-major L x p.
-__device__ void gram_small(const double* V, int L, int p, double* G) {
-  const int np = p * (p + 1) / 2;
-  for (int e = threadIdx.x; e < np; e += kEigThreads) {
-    int j1 = 0, rem = e;
-    while (rem >= p - j1) {
-      rem -= p - j1;
-      ++j1;
+// out[a][b] = sum_i X[i][a] * Y[i][b] for a <= b (PS x PS, symmetric fill).
+// Each thread owns one (a, b) pair and walks the rows with 16-byte loads.
+template <int PS, bool SYM_AVG>
+__device__ __forceinline__ void crossprod(const double* X, const double* Y, int L, double* out) {
+  constexpr int NP = PS * (PS + 1) / 2;
+  for (int e = threadIdx.x; e < NP; e += kEigThreads) {
+    int a = 0, rem = e;
+    while (rem >= PS - a) {
+      rem -= PS - a;
+      ++a;
     }
-    const int j2 = j1 + rem;
-    double s0 = 0.0, s1 = 0.0;
+    const int b = a + rem;
+    double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
     int i = 0;
     for (; i + 1 < L; i += 2) {
-      s0 = fma(V[i * p + j1], V[i * p + j2], s0);
-      s1 = fma(V[(i + 1) * p + j1], V[(i + 1) * p + j2], s1);
+      s0 = fma(X[i * PS + a], Y[i * PS + b], s0);
+      s1 = fma(X[(i + 1) * PS + a], Y[(i + 1) * PS + b], s1);
+      if (SYM_AVG) {
+        t0 = fma(X[i * PS + b], Y[i * PS + a], t0);
+        t1 = fma(X[(i + 1) * PS + b], Y[(i + 1) * PS + a], t1);
+      }
     }
-    if (i < L) s0 = fma(V[i * p + j1], V[i * p + j2], s0);
-    G[j1 * p + j2] = s0 + s1;
-    G[j2 * p + j1] = s0 + s1;
+    if (i < L) {
+      s0 = fma(X[i * PS + a], Y[i * PS + b], s0);
+      if (SYM_AVG) t0 = fma(X[i * PS + b], Y[i * PS + a], t0);
+    }
+    const double v = SYM_AVG ? 0.5 * ((s0 + s1) + (t0 + t1)) : (s0 + s1);
+    out[a * PS + b] = v;
+    out[b * PS + a] = v;
   }
 }
 
-// One Cholesky-QR pass on V (L x p), in place.
-__device__ void cholqr_pass(EigMem& m, int L, int p) {
+// One Cholesky-QR pass on V (L x PS), in place.
+template <int PS>
+__device__ __forceinline__ void cholqr_pass(EigMem<PS>& m, int L) {
   double* V = m.V;
   double* H = m.H;
   EigSmall& sh = *m.sm;
-  gram_small(V, L, p, H);
+  const int tid = threadIdx.x;
+  crossprod<PS, false>(V, V, L, H);
   __syncthreads();
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    for (int j = lane; j < p; j += 64) {
-      const double d = H[j * p + j];
-      sh.dscale[j] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-    }
-    wave_fence();
-    for (int e = lane; e < p * p; e += 64) {
-      const int r = e / p, c = e % p;
-      H[e] *= sh.dscale[r] * sh.dscale[c];
-    }
-    wave_fence();
-    for (int j = 0; j < p; ++j) {
-      const double piv = H[j * p + j];
-      const bool dead = !(piv > 1e-15) || sh.dscale[j] == 0.0;
-      const double d = dead ? 0.0 : sqrt(piv);
-      wave_fence();
-      for (int i = j + 1 + lane; i < p; i += 64) H[i * p + j] = dead ? 0.0 : H[i * p + j] / d;
-      if (lane == 0) H[j * p + j] = dead ? 0.0 : d;
-      wave_fence();
-      const int w = p - j - 1;
-      for (int e = lane; e < w * w; e += 64) {
-        const int i = j + 1 + e / w;
-        const int k = j + 1 + e % w;
-        if (k <= i) H[i * p + k] -= H[i * p + j] * H[k * p + j];
-      }
-      wave_fence();
-    }
+  // Cholesky of D G D (D = diag(G)^{-1/2}), lower factor in place, whole block
+  if (tid < PS) {
+    const double d = H[tid * PS + tid];
+    sh.dscale[tid] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  // V <- V D R^{-1}; row i solves x R = v D (R upper = transpose of the factor in H)
+  for (int e = tid; e < PS * PS; e += kEigThreads) H[e] *= sh.dscale[e / PS] * sh.dscale[e % PS];
+  __syncthreads();
+  double minpiv = 1.0;  // smallest normalised pivot of a live column (same in every thread)
+  for (int j = 0; j < PS; ++j) {
+    const double piv = H[j * PS + j];
+    const bool dead = !(piv > 1e-15) || sh.dscale[j] == 0.0;
+    if (sh.dscale[j] != 0.0) minpiv = fmin(minpiv, piv);
+    const double inv = dead ? 0.0 : 1.0 / sqrt(piv);
+    __syncthreads();  // every thread has read the pivot
+    if (tid > j && tid < PS) H[tid * PS + j] *= inv;
+    if (tid == 0) H[j * PS + j] = dead ? 0.0 : sqrt(piv);
+    __syncthreads();
+    // trailing update of the lower triangle, rows and columns j+1..PS-1
+    const int w = PS - j - 1;
+    for (int e = tid; e < w * w; e += kEigThreads) {
+      const int i = j + 1 + e / w;
+      const int k = j + 1 + e % w;
+      if (k <= i) H[i * PS + k] -= H[i * PS + j] * H[k * PS + j];
+    }
+    __syncthreads();
+  }
+  // reciprocal diagonal for the solve (cs_c is free outside the Jacobi sweep)
+  if (tid < PS) {
+    const double r = H[tid * PS + tid];
+    sh.cs_c[tid] = r > 0.0 ? 1.0 / r : 0.0;
+  }
+  if (tid == 0) sh.minpiv = minpiv;
+  __syncthreads();
+  // V <- V D R^{-1}; row i solves x R = v D (R = transpose of the lower factor in H)
   for (int i = threadIdx.x; i < L; i += kEigThreads) {
-    double x[kEigPMax];
+    double x[PS];
 #pragma unroll
-    for (int j = 0; j < kEigPMax; ++j) x[j] = (j < p) ? V[i * p + j] * sh.dscale[j] : 0.0;
+    for (int j = 0; j < PS; ++j) x[j] = V[i * PS + j] * sh.dscale[j];
 #pragma unroll
-    for (int j = 0; j < kEigPMax; ++j) {
-      if (j < p) {
-        double s = x[j];
+    for (int j = 0; j < PS; ++j) {
+      double s = x[j];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s -= x[k] * H[j * p + k];
-        const double rjj = H[j * p + j];
-        x[j] = rjj > 0.0 ? s / rjj : 0.0;
-      }
+      for (int k = 0; k < j; ++k) s -= x[k] * H[j * PS + k];
+      x[j] = s * sh.cs_c[j];
     }
 #pragma unroll
-    for (int j = 0; j < kEigPMax; ++j)
-      if (j < p) V[i * p + j] = x[j];
+    for (int j = 0; j < PS; ++j) V[i * PS + j] = x[j];
   }
   __syncthreads();
 }
 
-__device__ void orth(EigMem& m, int L, int p) {
-  cholqr_pass(m, L, p);
-  cholqr_pass(m, L, p);
+// Cholesky-QR, repeated once unless the first pass saw a well-conditioned
+// block (every normalised pivot >= 1/2, i.e. each column keeps at least
+// 1/sqrt(2) of its norm outside the span of the previous ones): then one pass
+// already leaves V orthonormal to rounding.
+template <int PS>
+__device__ __forceinline__ void orth(EigMem<PS>& m, int L) {
+  cholqr_pass<PS>(m, L);
+  if (m.sm->minpiv < 0.5) cholqr_pass<PS>(m, L);
 }
 
-// Cyclic Jacobi (round-robin pairs) on H (p x p) by wavefront 0; Z accumulates
-// the rotations.
-__device__ void jacobi_wave(EigMem& m, int p, int maxsweep) {
+// Cyclic Jacobi (round-robin pairs) on H (PS x PS) by the whole block; Z
+// accumulates the rotations.
+template <int PS>
+__device__ __forceinline__ void jacobi_block(EigMem<PS>& m, int maxsweep) {
   EigSmall& sh = *m.sm;
-  const int lane = threadIdx.x;
-  const int pe = p + (p & 1);
+  const int tid = threadIdx.x;
   double* Z = m.Z;
-  for (int e = lane; e < p * p; e += 64) Z[e] = (e / p == e % p) ? 1.0 : 0.0;
-  wave_fence();
+  for (int e = tid; e < PS * PS; e += kEigThreads) Z[e] = (e / PS == e % PS) ? 1.0 : 0.0;
+  __syncthreads();
   double* Hc = m.H;
   double* Hn = m.H2;
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int e = lane; e < p * p; e += 64) {
+    for (int e = tid; e < PS * PS; e += kEigThreads) {
       const double v = Hc[e];
-      if (e / p == e % p)
+      if (e / PS == e % PS)
         dia += v * v;
       else
         off += v * v;
     }
     off = wave_sum(off);
     dia = wave_sum(dia);
-    if (off <= 1e-30 * dia || off == 0.0) break;
-    for (int r = 0; r < pe - 1; ++r) {
-      if (lane < pe / 2) {
-        auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + r) % (pe - 1); };
-        int a = slot(lane), b = slot(pe - 1 - lane);
+    if ((tid & 63) == 0) {
+      sh.red[2 * (tid >> 6)] = off;
+      sh.red[2 * (tid >> 6) + 1] = dia;
+    }
+    __syncthreads();
+    off = (sh.red[0] + sh.red[2]) + (sh.red[4] + sh.red[6]);
+    dia = (sh.red[1] + sh.red[3]) + (sh.red[5] + sh.red[7]);
+    __syncthreads();
+    // off-diagonal norm <= 1e-13 of the diagonal's: the Ritz pairs are then
+    // exact to far below the residual test that decides convergence
+    if (off <= 1e-26 * dia || off == 0.0) break;
+    for (int r = 0; r < PS - 1; ++r) {
+      if (tid < PS / 2) {
+        const int lane = tid;
+        auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + r) % (PS - 1); };
+        int a = slot(lane), b = slot(PS - 1 - lane);
         if (a > b) {
           const int t = a;
           a = b;
           b = t;
         }
         double c = 1.0, s = 0.0;
-        if (b < p) {
-          const double apq = Hc[a * p + b];
-          if (apq != 0.0) {
-            const double tau = (Hc[b * p + b] - Hc[a * p + a]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+        const double apq = Hc[a * PS + b];
+        if (apq != 0.0) {
+          const double tau = (Hc[b * PS + b] - Hc[a * PS + a]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
         }
         // rotation J: J[a][a] = c, J[b][a] = -s, J[a][b] = s, J[b][b] = c
-        if (a < p) {
-          sh.partner[a] = b < p ? b : a;
-          sh.cs_c[a] = c;
-          sh.cs_s[a] = b < p ? -s : 0.0;
-        }
-        if (b < p) {
-          sh.partner[b] = a;
-          sh.cs_c[b] = c;
-          sh.cs_s[b] = s;
-        }
+        sh.partner[a] = b;
+        sh.cs_c[a] = c;
+        sh.cs_s[a] = -s;
+        sh.partner[b] = a;
+        sh.cs_c[b] = c;
+        sh.cs_s[b] = s;
       }
-      wave_fence();
-      for (int e = lane; e < p * p; e += 64) {
-        const int x = e / p, y = e % p;
+      __syncthreads();
+      for (int e = tid; e < PS * PS; e += kEigThreads) {
+        const int x = e / PS, y = e % PS;
         const int xp = sh.partner[x], yp = sh.partner[y];
         const double ax = sh.cs_c[x], bx = sh.cs_s[x], ay = sh.cs_c[y], by = sh.cs_s[y];
-        double v = ax * ay * Hc[x * p + y];
-        if (yp != y) v += ax * by * Hc[x * p + yp];
-        if (xp != x) v += bx * ay * Hc[xp * p + y];
-        if (xp != x && yp != y) v += bx * by * Hc[xp * p + yp];
-        if (xp == y && x != y) v = 0.0;  // the annihilated pair
+        double v = ax * ay * Hc[x * PS + y] + ax * by * Hc[x * PS + yp] +
+                   bx * ay * Hc[xp * PS + y] + bx * by * Hc[xp * PS + yp];
+        if (xp == y) v = 0.0;  // the annihilated pair
         Hn[e] = v;
       }
-      for (int e = lane; e < p * p; e += 64) {
-        const int i = e / p, y = e % p;
+      // Z <- Z J: a thread owns (row i, pair) updates for the first member of each pair
+      for (int e = tid; e < PS * PS; e += kEigThreads) {
+        const int i = e / PS, y = e % PS;
         const int yp = sh.partner[y];
-        if (yp < y) continue;
-        const double zy = Z[i * p + y];
-        if (yp == y) {
-          Z[i * p + y] = sh.cs_c[y] * zy;
-        } else {
-          const double zyp = Z[i * p + yp];
-          Z[i * p + y] = sh.cs_c[y] * zy + sh.cs_s[y] * zyp;
-          Z[i * p + yp] = sh.cs_c[yp] * zyp + sh.cs_s[yp] * zy;
+        if (yp > y) {
+          const double zy = Z[i * PS + y], zyp = Z[i * PS + yp];
+          Z[i * PS + y] = sh.cs_c[y] * zy + sh.cs_s[y] * zyp;
+          Z[i * PS + yp] = sh.cs_c[yp] * zyp + sh.cs_s[yp] * zy;
         }
       }
-      wave_fence();
+      __syncthreads();
       double* t = Hc;
       Hc = Hn;
       Hn = t;
     }
   }
   if (Hc != m.H) {
-    for (int e = lane; e < p * p; e += 64) m.H[e] = Hc[e];
-    wave_fence();
-  }
-}
-
-// Fill columns [j0, p) of V with deterministic pseudo-random values.
-__device__ void fill_columns(double* V, int L, int p, int j0, uint64_t seed) {
-  for (int e = threadIdx.x; e < L * (p - j0); e += kEigThreads) {
-    const int i = e / (p - j0), j = j0 + e % (p - j0);
-    V[i * p + j] = hash_unit((seed << 40) ^ ((uint64_t)i << 20) ^ (uint64_t)j);
-  }
-}
-
-// Re-lay V from row stride p_old to row stride p_new (p_new > p_old), in place.
-__device__ void widen_rows(double* V, int L, int p_old, int p_new) {
-  // rows move to higher addresses: walk rows from the last one, one row per step
-  for (int i = L - 1; i >= 0; --i) {
-    double v = 0.0;
-    const int j = threadIdx.x;
-    if (j < p_old) v = V[i * p_old + j];
-    __syncthreads();
-    if (j < p_old) V[i * p_new + j] = v;
+    for (int e = tid; e < PS * PS; e += kEigThreads) m.H[e] = Hc[e];
     __syncthreads();
   }
 }
 
+// kLds: V and W live in LDS (a compile-time choice, so that every access to
+// them is an LDS instruction rather than a generic one).
+template <int PS, bool kLds>
 __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     const EigJob* __restrict__ jobs, int job0, const double* __restrict__ S_base,
     const double* __restrict__ V0_base, double* __restrict__ F_base, double* __restrict__ ev_base,
     double* __restrict__ work_base, int* __restrict__ status, int* __restrict__ iters_out,
-    int maxit, double tol, int vw_in_lds) {
+    int maxit, double tol) {
   extern __shared__ double dyn[];
   __shared__ EigSmall small;
   const int mi = job0 + blockIdx.x;
@@ -305,54 +303,59 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
   double* ev = ev_base + job.ev_off;
   const int tid = threadIdx.x;
 
-  EigMem m;
+  EigMem<PS> m;
   m.H = dyn;
-  m.Z = dyn + pmax * pmax;
-  m.H2 = dyn + 2 * pmax * pmax;
-  if (vw_in_lds) {
-    m.V = dyn + 3 * pmax * pmax;
-  } else {
+  m.Z = dyn + PS * PS;
+  m.H2 = dyn + 2 * PS * PS;
+  if constexpr (kLds)
+    m.V = dyn + 3 * PS * PS;
+  else
     m.V = work_base + job.work_off;
-  }
-  m.W = m.V + (int64_t)L * pmax;
+  m.W = m.V + (int64_t)L * PS;
   m.sm = &small;
   EigSmall& sh = small;
 
-  // start block: p = L (full Jacobi) when L <= p_max; warm: K + 4; cold: p_max
+  // start block: p = L (full Jacobi) when L <= p_max; warm: the K previous
+  // factors; cold: p_max columns
   int p;
   if (pmax == L)
     p = L;
   else if (V0)
-    p = min(pmax, K + 4);
+    p = K;
   else
     p = pmax;
   bool grown = (p == pmax);
-  for (int e = tid; e < L * p; e += kEigThreads) {
-    const int i = e / p, j = e % p;
-    double v;
-    if (p == L)
-      v = (i == j) ? 1.0 : 0.0;
-    else if (V0 && j < K)
-      v = V0[(int64_t)i * K + j];
-    else
-      v = hash_unit(((uint64_t)mi << 40) ^ ((uint64_t)i << 20) ^ (uint64_t)j);
+  for (int e = tid; e < L * PS; e += kEigThreads) {
+    const int i = e / PS, j = e % PS;
+    double v = 0.0;
+    if (j < p) {
+      if (p == L)
+        v = (i == j) ? 1.0 : 0.0;
+      else if (V0 && j < K)
+        v = V0[(int64_t)i * K + j];
+      else
+        v = hash_unit(((uint64_t)mi << 40) ^ ((uint64_t)i << 20) ^ (uint64_t)j);
+    }
     m.V[e] = v;
   }
   __syncthreads();
-  if (p < L) orth(m, L, p);
+  if (p < L) orth<PS>(m, L);
 
   int converged = 0;
   int used = 0;
   for (int it = 0; it < 2 * maxit; ++it) {
     used = it;
     if (it == maxit && !grown) {
-      // not converged with the small block: widen to p_max with fresh columns
-      widen_rows(m.V, L, p, pmax);
-      fill_columns(m.V, L, pmax, p, (uint64_t)mi + 7777);
+      // not converged with the small block: add fill columns up to p_max
+      for (int e = tid; e < L * PS; e += kEigThreads) {
+        const int i = e / PS, j = e % PS;
+        if (j >= p && j < pmax)
+          m.V[e] = hash_unit(((uint64_t)(mi + 7777) << 40) ^ ((uint64_t)i << 20) ^ (uint64_t)j);
+      }
       p = pmax;
       grown = true;
       __syncthreads();
-      orth(m, L, p);
+      orth<PS>(m, L);
     } else if (it == maxit) {
       break;
     }
@@ -360,105 +363,81 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     double* W = m.W;
     // ---- W = S V (S symmetric: threads walk rows i, reading S[l][i] coalesced)
     for (int i = tid; i < L; i += kEigThreads) {
-      double acc[kEigPMax];
+      double acc[PS];
 #pragma unroll
-      for (int j = 0; j < kEigPMax; ++j) acc[j] = 0.0;
-      // S comes from global memory: 16 loads in flight per step
-      constexpr int kPre = 16;
+      for (int j = 0; j < PS; ++j) acc[j] = 0.0;
+      constexpr int kPre = 8;
       for (int l0 = 0; l0 < L; l0 += kPre) {
         double sv[kPre];
 #pragma unroll
         for (int u = 0; u < kPre; ++u) sv[u] = (l0 + u < L) ? S[(int64_t)(l0 + u) * L + i] : 0.0;
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
-          if (l0 + u < L) {
-            const double* vr = V + (l0 + u) * p;
+          const int l = min(l0 + u, L - 1);  // sv is 0 past the end
+          const double* vr = V + l * PS;
 #pragma unroll
-            for (int j = 0; j < kEigPMax; ++j)
-              if (j < p) acc[j] = fma(sv[u], vr[j], acc[j]);
-          }
+          for (int j = 0; j < PS; ++j) acc[j] = fma(sv[u], vr[j], acc[j]);
         }
       }
 #pragma unroll
-      for (int j = 0; j < kEigPMax; ++j)
-        if (j < p) W[i * p + j] = acc[j];
+      for (int j = 0; j < PS; ++j) W[i * PS + j] = acc[j];
     }
     __syncthreads();
     // ---- H = V^T W (symmetrised)
-    {
-      const int np = p * (p + 1) / 2;
-      for (int e = tid; e < np; e += kEigThreads) {
-        int j1 = 0, rem = e;
-        while (rem >= p - j1) {
-          rem -= p - j1;
-          ++j1;
-        }
-        const int j2 = j1 + rem;
-        double s12 = 0.0, s21 = 0.0;
-        for (int i = 0; i < L; ++i) {
-          s12 = fma(V[i * p + j1], W[i * p + j2], s12);
-          s21 = fma(V[i * p + j2], W[i * p + j1], s21);
-        }
-        const double h = 0.5 * (s12 + s21);
-        m.H[j1 * p + j2] = h;
-        m.H[j2 * p + j1] = h;
-      }
-    }
+    crossprod<PS, true>(V, W, L, m.H);
     __syncthreads();
-    if (tid < 64) {
-      jacobi_wave(m, p, 30);
-      for (int j = tid; j < p; j += 64) sh.theta[j] = m.H[j * p + j];
-      wave_fence();
-      for (int j = tid; j < p; j += 64) {
-        const double tj = sh.theta[j];
-        int rank = 0;
-        for (int i = 0; i < p; ++i) {
-          const double ti = sh.theta[i];
-          rank += (ti > tj) || (ti == tj && i < j);
-        }
-        sh.perm[rank] = j;
+    jacobi_block<PS>(m, 30);
+    if (tid < PS) sh.theta[tid] = m.H[tid * PS + tid];
+    __syncthreads();
+    if (tid < PS) {
+      const int j = tid;
+      const double tj = sh.theta[j];
+      int rank = 0;
+      for (int i = 0; i < PS; ++i) {
+        const double ti = sh.theta[i];
+        // padded columns (j >= p) rank last
+        const bool before = (i < p) && ((j >= p) || ti > tj || (ti == tj && i < j));
+        rank += before || (j >= p && i >= p && i < j);
       }
+      sh.perm[rank] = j;
     }
     __syncthreads();
     // ---- Ritz vectors: V <- V Z(:, perm), W <- W Z(:, perm)
     for (int i = tid; i < L; i += kEigThreads) {
-      double xv[kEigPMax], xw[kEigPMax];
+      double xv[PS], xw[PS];
 #pragma unroll
-      for (int j = 0; j < kEigPMax; ++j) {
-        xv[j] = (j < p) ? V[i * p + j] : 0.0;
-        xw[j] = (j < p) ? W[i * p + j] : 0.0;
+      for (int j = 0; j < PS; ++j) {
+        xv[j] = V[i * PS + j];
+        xw[j] = W[i * PS + j];
       }
-      for (int c = 0; c < p; ++c) {
+#pragma unroll 4
+      for (int c = 0; c < PS; ++c) {
         const int src = sh.perm[c];
         double sv = 0.0, sw = 0.0;
 #pragma unroll
-        for (int j = 0; j < kEigPMax; ++j) {
-          if (j < p) {
-            const double z = m.Z[j * p + src];
-            sv = fma(xv[j], z, sv);
-            sw = fma(xw[j], z, sw);
-          }
+        for (int j = 0; j < PS; ++j) {
+          const double z = m.Z[j * PS + src];
+          sv = fma(xv[j], z, sv);
+          sw = fma(xw[j], z, sw);
         }
-        V[i * p + c] = sv;
-        W[i * p + c] = sw;
+        V[i * PS + c] = sv;
+        W[i * PS + c] = sw;
       }
     }
     __syncthreads();
     // ---- residuals of the leading K Ritz pairs
     {
-      double part[kEigPMax];
+      double part[PS];
 #pragma unroll
-      for (int j = 0; j < kEigPMax; ++j) part[j] = 0.0;
+      for (int j = 0; j < PS; ++j) part[j] = 0.0;
       for (int i = tid; i < L; i += kEigThreads) {
 #pragma unroll
-        for (int j = 0; j < kEigPMax; ++j) {
-          if (j < K) {
-            const double r = W[i * p + j] - sh.theta[sh.perm[j]] * V[i * p + j];
-            part[j] = fma(r, r, part[j]);
-          }
+        for (int j = 0; j < PS; ++j) {
+          const double r = W[i * PS + j] - sh.theta[sh.perm[j]] * V[i * PS + j];
+          part[j] = fma(r, r, part[j]);
         }
       }
-      block_sum_vec(part, K, sh.red, sh.dscale);
+      block_sum_vec<PS>(part, sh.red, sh.dscale);
       if (tid == 0) {
         const double t0 = fabs(sh.theta[sh.perm[0]]);
         double worst = 0.0;
@@ -480,9 +459,9 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
       break;
     }
     // ---- power step: V = orth(W)
-    for (int e = tid; e < L * p; e += kEigThreads) V[e] = W[e];
+    for (int e = tid; e < L * PS; e += kEigThreads) V[e] = W[e];
     __syncthreads();
-    orth(m, L, p);
+    orth<PS>(m, L);
   }
 
   // ---- output: first K columns, sign rule, eigenvalues
@@ -491,7 +470,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     double best = -1.0;
     int bi = 0x7fffffff;
     for (int i = tid; i < L; i += kEigThreads) {
-      const double a = fabs(V[i * p + j]);
+      const double a = fabs(V[i * PS + j]);
       if (a > best || (a == best && i < bi)) {
         best = a;
         bi = i;
@@ -521,11 +500,11 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
           i0 = oi;
         }
       }
-      sh.dscale[0] = V[i0 * p + j] < 0.0 ? -1.0 : 1.0;
+      sh.dscale[0] = V[i0 * PS + j] < 0.0 ? -1.0 : 1.0;
     }
     __syncthreads();
     const double sg = sh.dscale[0];
-    for (int i = tid; i < L; i += kEigThreads) F[(int64_t)i * K + j] = sg * V[i * p + j];
+    for (int i = tid; i < L; i += kEigThreads) F[(int64_t)i * K + j] = sg * V[i * PS + j];
     __syncthreads();
   }
   if (tid < K) ev[tid] = sh.theta[sh.perm[tid]];
@@ -543,43 +522,93 @@ int eig_block_size(int L, int K, int64_t rank_bound) {
   return (int)std::max<int64_t>(p, K);
 }
 
-size_t eig_lds_bytes(int L, int p, bool vw_in_lds) {
-  return sizeof(double) * ((size_t)3 * p * p + (vw_in_lds ? (size_t)2 * L * p : 0));
+namespace {
+
+int padded(int p) { return (p + 7) / 8 * 8; }
+
+size_t eig_lds_bytes(int L, int PS, bool vw_in_lds) {
+  return sizeof(double) * ((size_t)3 * PS * PS + (vw_in_lds ? (size_t)2 * L * PS : 0));
 }
 
-static int g_lds_limit = 0;  // dynamic LDS bytes available to one workgroup
+int g_lds_limit = 0;  // dynamic LDS bytes available to one workgroup
 
-bool eig_vw_fits_lds(int L, int p) {
-  return eig_lds_bytes(L, p, true) <= (size_t)g_lds_limit;
+template <int PS>
+hipError_t set_attr(int lim) {
+  hipError_t e = hipFuncSetAttribute((const void*)eig_subspace<PS, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)eig_subspace<PS, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
+
+hipError_t init_lds_limit() {
+  if (g_lds_limit != 0) return hipSuccess;
+  int dev = 0, per_block = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  int lim = std::min(per_block, kEigLdsMax) - (int)sizeof(EigSmall);
+  if (lim > 64 * 1024) {
+    hipError_t a = set_attr<8>(lim);
+    if (a == hipSuccess) a = set_attr<16>(lim);
+    if (a == hipSuccess) a = set_attr<24>(lim);
+    if (a == hipSuccess) a = set_attr<32>(lim);
+    if (a == hipSuccess) a = set_attr<40>(lim);
+    if (a == hipSuccess) a = set_attr<48>(lim);
+    if (a != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 64 * 1024 - (int)sizeof(EigSmall);
+    }
+  }
+  g_lds_limit = lim;
+  return hipSuccess;
+}
+
+template <int PS>
+void launch_ps(int count, const EigJob* jobs_dev, int job0, int Lmax, const double* S_base,
+               const double* V0_base, double* F_base, double* ev_base, double* work_base,
+               int* status, int* iters, int maxit, double tol, hipStream_t st) {
+  const bool in_lds = eig_lds_bytes(Lmax, PS, true) <= (size_t)g_lds_limit;
+  const size_t lds = eig_lds_bytes(Lmax, PS, in_lds);
+  if (in_lds)
+    hipLaunchKernelGGL((eig_subspace<PS, true>), dim3(count), dim3(kEigThreads), lds, st,
+                       jobs_dev, job0, S_base, V0_base, F_base, ev_base, work_base, status, iters,
+                       maxit, tol);
+  else
+    hipLaunchKernelGGL((eig_subspace<PS, false>), dim3(count), dim3(kEigThreads), lds, st,
+                       jobs_dev, job0, S_base, V0_base, F_base, ev_base, work_base, status, iters,
+                       maxit, tol);
+}
+
+}  // namespace
+
+size_t eig_work_elems(int L, int p) { return (size_t)2 * L * padded(p); }
 
 hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int pmax,
                       const double* S_base, const double* V0_base, double* F_base,
                       double* ev_base, double* work_base, int* status, int* iters, int maxit,
                       double tol, hipStream_t st) {
   if (count == 0) return hipSuccess;
-  if (g_lds_limit == 0) {
-    int dev = 0, per_block = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-      e = hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    if (e != hipSuccess) return e;
-    int lim = std::min(per_block, kEigLdsMax) - (int)sizeof(EigSmall);
-    if (lim > 64 * 1024) {
-      e = hipFuncSetAttribute((const void*)eig_subspace,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        lim = 64 * 1024 - (int)sizeof(EigSmall);
-      }
-    }
-    g_lds_limit = lim;
+  hipError_t e = init_lds_limit();
+  if (e != hipSuccess) return e;
+  const int PS = padded(pmax);
+#define TK_EIG_CASE(P)                                                                    \
+  case P:                                                                                 \
+    launch_ps<P>(count, jobs_dev, job0, Lmax, S_base, V0_base, F_base, ev_base, work_base, \
+                 status, iters, maxit, tol, st);                                          \
+    break;
+  switch (PS) {
+    TK_EIG_CASE(8)
+    TK_EIG_CASE(16)
+    TK_EIG_CASE(24)
+    TK_EIG_CASE(32)
+    TK_EIG_CASE(40)
+    TK_EIG_CASE(48)
+    default:
+      return hipErrorInvalidValue;
   }
-  const bool in_lds = eig_vw_fits_lds(Lmax, pmax);
-  const size_t lds = eig_lds_bytes(Lmax, pmax, in_lds);
-  hipLaunchKernelGGL(eig_subspace, dim3(count), dim3(kEigThreads), lds, st, jobs_dev, job0,
-                     S_base, V0_base, F_base, ev_base, work_base, status, iters, maxit, tol,
-                     in_lds ? 1 : 0);
+#undef TK_EIG_CASE
   return hipGetLastError();
 }
 

@@ -92,6 +92,7 @@ struct tk_ctx {
   double* F64a = nullptr;   // current factors (FP64 master)
   double* F64b = nullptr;   // next factors
   void* Fc = nullptr;       // compute-precision copy of the current factors
+  void* Fcb = nullptr;      // compute-precision copy of the next factors
   double* S = nullptr;      // Gram matrices
   double* ev = nullptr;     // eigenvalues
   double* eigwork = nullptr;
@@ -115,15 +116,21 @@ struct tk_ctx {
   double eig_tol = 1e-11;
   int Lmax = 0, pmax = 0;
 
-  // Side stream for the per-leaf eigensolves (default priority), joined back
-  // into `st` with events at the end of every tree pass.
+  // Side stream for the per-leaf eigensolves (default priority).  The solve
+  // for mode n starts when its Gram is formed (ev_leaf[n]) and signals
+  // ev_fac[n] once the new factor (FP64 and compute copy) is written; the main
+  // stream waits on ev_fac[n] only before it next uses factor n, so a solve
+  // overlaps the rest of its own tree pass and the start of the next one.
   hipStream_t side = nullptr;
   hipEvent_t ev_leaf[TK_MAX_MODES] = {};
-  hipEvent_t ev_join = nullptr;
+  hipEvent_t ev_fac[TK_MAX_MODES] = {};
+  bool pending[TK_MAX_MODES] = {};
+  int passes = 0;  // pipelined passes so far (alternates the root-subtree order)
 
   ~tk_ctx() {
     if (side) (void)hipStreamSynchronize(side);
-    void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc, S, ev, eigwork, status, jobs,
+    void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc,
+                    wdtype == TK_F64 ? nullptr : Fcb, S, ev, eigwork, status, jobs,
                     jobs_cold, gpart, rpart, scal, core};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
@@ -131,7 +138,8 @@ struct tk_ctx {
       if (p) (void)hipFree(p);
     for (hipEvent_t e : ev_leaf)
       if (e) (void)hipEventDestroy(e);
-    if (ev_join) (void)hipEventDestroy(ev_join);
+    for (hipEvent_t e : ev_fac)
+      if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
   }
 
@@ -156,7 +164,23 @@ int refresh_compute_factors(tk_ctx* c) {
   return TK_OK;
 }
 
+// Make the main stream wait for the pending update of factor n (if any).
+int wait_factor(tk_ctx* c, int n) {
+  if (!c->pending[n]) return TK_OK;
+  TK_HIP(hipStreamWaitEvent(c->st, c->ev_fac[n], 0));
+  c->pending[n] = false;
+  return TK_OK;
+}
+
+// Make the main stream wait for every pending factor update.
+int join_factors(tk_ctx* c) {
+  for (int n = 0; n < c->s.N; ++n)
+    if (int rc = wait_factor(c, n)) return rc;
+  return TK_OK;
+}
+
 int check_status(tk_ctx* c) {
+  if (int rc = join_factors(c)) return rc;
   std::vector<int> st(c->s.N);
   TK_HIP(hipMemcpyAsync(st.data(), c->status, sizeof(int) * c->s.N, hipMemcpyDeviceToHost, c->st));
   TK_HIP(hipStreamSynchronize(c->st));
@@ -168,18 +192,41 @@ int check_status(tk_ctx* c) {
   return TK_OK;
 }
 
+// Execution order of the nodes: depth-first, root subtrees in plan order or,
+// with `reverse`, in reverse plan order (each subtree stays depth-first).
+std::vector<int> exec_order(const std::vector<tk_node>& nodes, bool reverse) {
+  std::vector<int> starts;
+  for (size_t u = 0; u < nodes.size(); ++u)
+    if (nodes[u].parent < 0) starts.push_back((int)u);
+  starts.push_back((int)nodes.size());
+  std::vector<int> order;
+  const int nsub = (int)starts.size() - 1;
+  for (int k = 0; k < nsub; ++k) {
+    const int r = reverse ? nsub - 1 - k : k;
+    for (int u = starts[r]; u < starts[r + 1]; ++u) order.push_back(u);
+  }
+  return order;
+}
+
 // One tree pass with the compute-precision factors in c->Fc.
 //   fold_dst >= 0: fold the core (G = Y_m x_m F_m^T) and store ||G||^2 in scal[fold_dst].
 //   keep: copy every leaf tensor to c->leaves.
-//   ev_t: optional per-node timing events (2 per node).
-//   eig_out: if set, every leaf's warm-started eigensolve (-> eig_out) runs on
-//   the side stream as soon as its Gram is formed, overlapping the rest of the
-//   tree; the pass ends by joining the side stream into c->st.
-int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, double* eig_out = nullptr) {
+//   ev_t: optional per-node timing events (2 per node, indexed by node).
+//   update: every leaf's warm-started eigensolve runs on the side stream as
+//   soon as its Gram is formed, writing the next factors (F64b, Fcb); at the
+//   end of the pass next and current factors swap and every factor is marked
+//   pending until its solve has finished.  Alternate passes run the root
+//   subtrees in reverse order so that a factor finished late in one pass is
+//   needed late in the next one.
+int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update = false) {
   const Shape& s = c->s;
   const auto& nodes = c->tree.nodes;
-  for (size_t u = 0; u < nodes.size(); ++u) {
+  const std::vector<int> order = exec_order(nodes, update && (c->passes % 2 == 1));
+  for (int u : order) {
     const tk_node& nd = nodes[u];
+    // the node reads factor nd.mode (a leaf also rewrites Gram buffer nd.mode,
+    // which the pending solve of that mode may still read)
+    if (int rc = wait_factor(c, nd.mode)) return rc;
     const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
     const int in_dt = nd.parent < 0 ? c->tdtype : c->wdtype;
     int64_t A, L, B;
@@ -195,12 +242,17 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, double* eig_
       if (keep)
         TK_HIP(hipMemcpyAsync(c->leaves[n], in, (size_t)c->leaf_elems[n] * dtype_size(in_dt),
                               hipMemcpyDeviceToDevice, c->st));
-      if (eig_out) {
+      if (update) {
         TK_HIP(hipEventRecord(c->ev_leaf[n], c->st));
         TK_HIP(hipStreamWaitEvent(c->side, c->ev_leaf[n], 0));
         const EigJob& j = c->jobs_h[n];
-        TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, eig_out, c->ev, c->eigwork,
+        TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, c->F64b, c->ev, c->eigwork,
                           c->status, c->status + s.N, c->maxit_warm, c->eig_tol, c->side));
+        if (c->wdtype != TK_F64)
+          TK_HIP(launch_convert(TK_F64, c->wdtype, c->F64b + c->fofs[n],
+                                (char*)c->Fcb + c->fofs[n] * dtype_size(c->wdtype),
+                                (int64_t)(c->fofs[n + 1] - c->fofs[n]), c->side));
+        TK_HIP(hipEventRecord(c->ev_fac[n], c->side));
       }
       if (fold_dst >= 0 && n == c->fold_leaf) {
         TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
@@ -210,9 +262,11 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, double* eig_
     }
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u + 1], c->st));
   }
-  if (eig_out) {
-    TK_HIP(hipEventRecord(c->ev_join, c->side));
-    TK_HIP(hipStreamWaitEvent(c->st, c->ev_join, 0));
+  if (update) {
+    std::swap(c->F64a, c->F64b);
+    std::swap(c->Fc, c->Fcb);
+    for (int n = 0; n < s.N; ++n) c->pending[n] = true;
+    c->passes++;
   }
   return TK_OK;
 }
@@ -360,16 +414,23 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     j.F_off = (int64_t)c->fofs[n];
     j.ev_off = (int64_t)c->kofs[n];
     j.work_off = (int64_t)work;
-    work += (size_t)2 * j.L * j.p;
+    work += eig_work_elems(j.L, j.p);
     c->Lmax = std::max(c->Lmax, j.L);
     c->pmax = std::max(c->pmax, j.p);
   }
+  // cold starts (HOSVD) use the full block; warm starts (previous factors)
+  // need only K columns plus a little room to grow, which keeps the blocks in LDS
   std::vector<EigJob> cold = c->jobs_h;
+  for (int n = 0; n < N; ++n) {
+    EigJob& j = c->jobs_h[n];
+    if (j.p != j.L) j.p = std::max(j.K, std::min(j.p, j.K + 4));
+  }
   {
     hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
-    for (int n = 0; n < N && e == hipSuccess; ++n)
+    for (int n = 0; n < N && e == hipSuccess; ++n) {
       e = hipEventCreateWithFlags(&c->ev_leaf[n], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fac[n], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
       delete c;
       return fail(TK_EDEVICE, "stream/event creation failed: %s", hipGetErrorString(e));
@@ -393,6 +454,7 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   if ((rc = dalloc((void**)&c->F64b, sizeof(double) * c->fofs[N]))) return bail(rc);
   if (c->wdtype != TK_F64) {
     if ((rc = dalloc(&c->Fc, wsz * c->fofs[N]))) return bail(rc);
+    if ((rc = dalloc(&c->Fcb, wsz * c->fofs[N]))) return bail(rc);
   }
   if ((rc = dalloc((void**)&c->S, sizeof(double) * c->sofs[N]))) return bail(rc);
   if ((rc = dalloc((void**)&c->ev, sizeof(double) * c->kofs[N]))) return bail(rc);
@@ -404,7 +466,10 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   if ((rc = dalloc((void**)&c->rpart, sizeof(double) * sumsq_partials()))) return bail(rc);
   if ((rc = ensure_scal(c, 64))) return bail(rc);
   if ((rc = dalloc(&c->core, wsz * (size_t)c->core_elems))) return bail(rc);
-  if (c->wdtype == TK_F64) c->Fc = nullptr;
+  if (c->wdtype == TK_F64) {  // the FP64 masters double as compute copies
+    c->Fc = c->F64a;
+    c->Fcb = c->F64b;
+  }
 
   {
     hipError_t e = hipMemcpyAsync(c->jobs, c->jobs_h.data(), sizeof(EigJob) * N,
@@ -453,7 +518,6 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     if ((rc = run_eig(c, false, c->F64a, c->maxit_cold))) return bail(rc);
     if ((rc = check_status(c))) return bail(rc);
   }
-  if (c->wdtype == TK_F64) c->Fc = c->F64a;
   if ((rc = refresh_compute_factors(c))) return bail(rc);
   double nt2 = 0.0;
   if (hipError_t e = hipMemcpyAsync(&nt2, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->st);
@@ -477,13 +541,11 @@ extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
   if (iters < 1) return fail(TK_EINVAL, "iters=%d < 1", iters);
   if (int rc = ensure_scal(c, iters + 2)) return rc;
   // scal[0] = ||T||^2 (kept), scal[1 + t] = ||G^(t)||^2, t = 0..iters
+  if (int rc = join_factors(c)) return rc;
   TK_HIP(launch_fill_int(c->status, c->s.N, 0, c->st));
-  for (int t = 0; t < iters; ++t) {
-    if (int rc = tree_pass(c, 1 + t, false, nullptr, c->F64b)) return rc;
-    std::swap(c->F64a, c->F64b);
-    if (c->wdtype == TK_F64) c->Fc = c->F64a;
-    if (int rc = refresh_compute_factors(c)) return rc;
-  }
+  for (int t = 0; t < iters; ++t)
+    if (int rc = tree_pass(c, 1 + t, false, nullptr, true)) return rc;
+  if (int rc = join_factors(c)) return rc;
   if (int rc = core_chain(c, 1 + iters)) return rc;
   std::vector<double> g2(iters + 1);
   TK_HIP(hipMemcpyAsync(g2.data(), c->scal + 1, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost,
@@ -499,6 +561,7 @@ extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
 extern "C" int tucker_error(tk_ctx* c, double* rel_err, double* normT, double* normG) {
   clear_error();
   if (!c) return fail(TK_EINVAL, "ctx is null");
+  if (int rc = join_factors(c)) return rc;
   if (!c->core_valid) {
     if (int rc = core_chain(c, 1)) return rc;
     double g2 = 0.0;
@@ -592,6 +655,7 @@ extern "C" int tk_get_factor(tk_ctx* c, int n, double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
   if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
+  if (int rc = join_factors(c)) return rc;
   TK_HIP(hipMemcpyAsync(host, c->F64a + c->fofs[n], sizeof(double) * (c->fofs[n + 1] - c->fofs[n]),
                         hipMemcpyDeviceToHost, c->st));
   TK_HIP(hipStreamSynchronize(c->st));
@@ -620,6 +684,7 @@ extern "C" int tk_set_factors(tk_ctx* c, const double* host) {
   if (!c || !host) return fail(TK_EINVAL, "null argument");
   for (size_t i = 0; i < c->fofs[c->s.N]; ++i)
     if (!std::isfinite(host[i])) return fail(TK_ENUMERIC, "factors hold NaN/Inf");
+  if (int rc = join_factors(c)) return rc;
   TK_HIP(hipMemcpyAsync(c->F64a, host, sizeof(double) * c->fofs[c->s.N], hipMemcpyHostToDevice, c->st));
   if (int rc = refresh_compute_factors(c)) return rc;
   TK_HIP(hipStreamSynchronize(c->st));
@@ -639,6 +704,7 @@ extern "C" int tk_tree_pass(tk_ctx* c) {
       if (int rc = dalloc(&c->leaves[n], (size_t)c->leaf_elems[n] * 8)) return rc;
     }
   }
+  if (int rc = join_factors(c)) return rc;
   if (int rc = tree_pass(c, -1, true, nullptr)) return rc;
   TK_HIP(hipStreamSynchronize(c->st));
   return TK_OK;
@@ -691,7 +757,8 @@ extern "C" int tk_profile_tree(tk_ctx* c, float* ms_out, int cap, int* n) {
   if (!ms_out) return TK_OK;
   std::vector<hipEvent_t> ev(2 * nn);
   for (auto& e : ev) TK_HIP(hipEventCreate(&e));
-  int rc = tree_pass(c, -1, false, ev.data());
+  int rc = join_factors(c);
+  if (rc == TK_OK) rc = tree_pass(c, -1, false, ev.data());
   if (rc == TK_OK) {
     hipError_t e = hipEventSynchronize(ev.back());
     if (e != hipSuccess) rc = fail(TK_EDEVICE, "profile sync: %s", hipGetErrorString(e));
@@ -775,14 +842,14 @@ extern "C" int tk_eig_leading(int count, int L, int K, const double* S, const do
     j.V0_off = V0 ? (int64_t)m * L * K : -1;
     j.F_off = (int64_t)m * L * K;
     j.ev_off = (int64_t)m * K;
-    j.work_off = (int64_t)m * 2 * L * p;
+    j.work_off = (int64_t)(m * eig_work_elems(L, p));
   }
   EigJob* jd = nullptr;
   double* work = nullptr;
   int* status = nullptr;
   int rc = TK_OK;
   if ((rc = dalloc((void**)&jd, sizeof(EigJob) * count))) return rc;
-  if ((rc = dalloc((void**)&work, sizeof(double) * 2 * (size_t)L * p * count)) ||
+  if ((rc = dalloc((void**)&work, sizeof(double) * eig_work_elems(L, p) * count)) ||
       (rc = dalloc((void**)&status, sizeof(int) * count))) {
     (void)hipFree(jd);
     if (work) (void)hipFree(work);

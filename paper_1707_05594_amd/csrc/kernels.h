@@ -34,6 +34,7 @@ hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int
                       double* ev_base, double* work_base, int* status, int* iters, int maxit,
                       double tol, hipStream_t st);
 int eig_block_size(int L, int K, int64_t rank_bound);
+size_t eig_work_elems(int L, int p);  // global work doubles one job may need
 int eig_max_K();
 
 // misc.hip
