@@ -121,7 +121,11 @@ void tk_plan_free(tk_plan* plan);
  *   plan : tree to execute (NULL: the DP optimum).  Must have been built for
  *          the same (N, L, K); its selected rank is copied, the plan may be freed.
  *   compute: TK_C_*.  Supported: F64 storage with TK_C_FP64; F32 or BF16
- *          storage with TK_C_FP32, TK_C_BF16, TK_C_BF16X3.
+ *          storage with TK_C_FP32, TK_C_BF16, TK_C_BF16X3.  In the BF16
+ *          modes the TTMs that form the core (the tree path to the leaf
+ *          that folds it, and the direct core chain) run at FP32: the error
+ *          is ||T||^2 - ||G||^2, so ||G||^2 needs more than BF16 accuracy.
+ *          Intermediates are stored FP32 in every non-FP64 mode.
  *   F0_host: NULL to start from HOSVD (F_n = leading K_n left singular vectors
  *          of T_(n)), or host FP64 factors F_0..F_{N-1} concatenated, each
  *          L_n x K_n row-major (checkpoint / resume).  Copied.
@@ -178,8 +182,13 @@ void hooi_free(tk_ctx* ctx);
  *   Out[a, k, b] = sum_l F[l, k] * In[a, l, b],  0 <= k < K.
  * in_dtype: TK_F64/TK_F32/TK_BF16 element type of In.  F: device, L x K
  * row-major FP64 when compute == TK_C_FP64, else FP32.  Out: device,
- * [A, K, B] of FP64 (compute FP64) or FP32.  K <= 512, L <= 65535.
- * In and Out must not overlap. */
+ * [A, K, B] of FP64 (compute FP64) or FP32.  K <= 4096; L <= 512 for
+ * TK_C_FP64, L <= 2048 otherwise.  In and Out must not overlap.
+ * TK_C_BF16 / TK_C_BF16X3 round (split) In and F to bfloat16 on the fly; a
+ * node whose B is not a multiple of 4 (or B == 1 with L not a multiple of 4)
+ * is computed with FP32 operands instead, which is at least as accurate.
+ * Errors: TK_EINVAL (null pointer, size < 1, unknown code), TK_EUNSUPPORTED
+ * (dtype/compute pair or size limit), TK_EDEVICE (launch failure). */
 int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
            const void* F, int64_t K, void* out, void* stream);
 

@@ -11,6 +11,8 @@ Distributed Tucker Decomposition for Dense Tensors", arXiv 1707.05594):
   dynamic program (Sec. 3.3, recurrence), chain and balanced trees (Sec. 3.2),
   and a brute-force enumerator of all trie-shaped TTM-trees (plain C,
   ``brute_plan.c``) used to pin the dynamic program.
+* ``oracle.precision`` -- exact float64 models of the BF16 and split-BF16
+  (bf16x3) TTM node: operand rounding to bfloat16 and the kept products.
 
 Only the test-suite, the package smoke check and the benchmark's CPU-baseline
 leg may import this package.  The product path never calls it and shares no

@@ -75,6 +75,13 @@ struct tk_ctx {
   Shape s;
   int tdtype = TK_F32;
   int compute = TK_C_FP32;
+  // Arithmetic of the core and the error (the folded-core path and the direct
+  // core chain).  The error comes from ||T||^2 - ||G||^2, whose absolute
+  // error is the relative error of ||G||^2; BF16 operands (2^-8) would make
+  // that larger than e^2 itself at the error levels of interest, so the BF16
+  // modes form the core at FP32.
+  int core_compute = TK_C_FP32;
+  std::vector<int> node_compute;  // per tree node: compute, or core_compute on the fold path
   int wdtype = TK_F32;  // element type of intermediates and compute-precision factors
   const void* T = nullptr;
   hipStream_t st = nullptr;
@@ -234,7 +241,7 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
     if (!nd.is_leaf) {
       // children of the root stream T (too large to stay in cache between them)
-      TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
+      TK_HIP(launch_ttm(in_dt, c->node_compute[u], in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
                         c->wsp(c->node_off[u]), c->st, nd.parent < 0));
     } else {
       const int n = nd.mode;
@@ -255,7 +262,7 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
         TK_HIP(hipEventRecord(c->ev_fac[n], c->side));
       }
       if (fold_dst >= 0 && n == c->fold_leaf) {
-        TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
+        TK_HIP(launch_ttm(in_dt, c->core_compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
         TK_HIP(launch_sumsq(c->wdtype, c->core, c->core_elems, c->rpart, c->scal + fold_dst,
                             c->st));
       }
@@ -283,7 +290,7 @@ int core_chain(tk_ctx* c, int dst) {
     int64_t A, L, B;
     view(s, pre, n, &A, &L, &B);
     void* out = (i == N - 1) ? c->core : c->wsp((i % 2 == 0) ? 0 : c->chain_a);
-    TK_HIP(launch_ttm(in_dt, c->compute, in, A, L, B, c->fc(n), s.K[n], out, c->st, i == 0));
+    TK_HIP(launch_ttm(in_dt, c->core_compute, in, A, L, B, c->fc(n), s.K[n], out, c->st, i == 0));
     pre |= 1u << n;
     in = out;
     in_dt = c->wdtype;
@@ -322,8 +329,6 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if ((tdtype == TK_F64) != (compute == TK_C_FP64))
     return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
-  if (compute == TK_C_BF16 || compute == TK_C_BF16X3)
-    return fail(TK_EUNSUPPORTED, "compute mode %d is not built", compute);
   const int maxL = compute == TK_C_FP64 ? 512 : ttm_max_L();
   for (int j = 0; j < N; ++j) {
     if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
@@ -374,6 +379,11 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
       c->fold_leaf = n;
     }
   }
+  c->core_compute = (compute == TK_C_BF16 || compute == TK_C_BF16X3) ? TK_C_FP32 : compute;
+  c->node_compute.assign(nodes.size(), compute);
+  for (size_t u = 0; u < nodes.size(); ++u)
+    if (nodes[u].is_leaf && nodes[u].mode == c->fold_leaf)
+      for (int v = (int)u; v >= 0; v = nodes[v].parent) c->node_compute[v] = c->core_compute;
   // direct core chain order: ascending K L / (L - K), modes with K = L last
   c->chain_order.resize(N);
   for (int j = 0; j < N; ++j) c->chain_order[j] = j;
@@ -794,11 +804,12 @@ extern "C" int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   if (compute == TK_C_FP64) {
     if (in_dtype != TK_F64) return fail(TK_EUNSUPPORTED, "FP64 compute needs FP64 input");
     if (L > 512) return fail(TK_EUNSUPPORTED, "FP64 TTM supports L <= 512");
-  } else if (compute == TK_C_FP32) {
-    if (in_dtype == TK_F64) return fail(TK_EUNSUPPORTED, "FP32 compute takes F32/BF16 input");
+  } else if (compute >= TK_C_FP32 && compute <= TK_C_BF16X3) {
+    if (in_dtype == TK_F64)
+      return fail(TK_EUNSUPPORTED, "compute mode %d takes F32/BF16 input", compute);
     if (L > ttm_max_L()) return fail(TK_EUNSUPPORTED, "L=%lld exceeds %d", (long long)L, ttm_max_L());
   } else {
-    return fail(TK_EUNSUPPORTED, "compute mode %d is not built", compute);
+    return fail(TK_EINVAL, "unknown compute mode %d", compute);
   }
   if (K > 4096) return fail(TK_EUNSUPPORTED, "K > 4096");
   if (A * B > ((int64_t)1 << 40)) return fail(TK_EINVAL, "tensor too large");

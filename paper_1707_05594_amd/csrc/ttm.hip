@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -171,6 +172,203 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l + j) * KG + g], x[j], acc[g]);
+  }
+  if (!active) return;
+  float* q = out + a * Kt;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) q[k] = acc[g][m];
+    }
+}
+
+// ------------------------------------------------------------- BF16 MFMA paths --
+// TK_C_BF16: both operands rounded to bfloat16 (round to nearest even), FP32
+// accumulation, on v_mfma_f32_4x4x4_16b_bf16: the 4x4x1 block structure of the
+// FP32 path with a reduction depth of four, so each MFMA consumes four
+// consecutive l of one column.  Lanes load the same coalesced 16-byte row
+// pieces as the FP32 wide path (four rows l..l+3) and transpose them in
+// registers into per-column operands; a row-path lane reads four consecutive
+// l of its own row directly.
+// TK_C_BF16X3: split-precision, a ~ a_hi + a_lo with a_hi = bf16(a),
+// a_lo = bf16(a - a_hi); a*b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (three MFMAs,
+// the dropped a_lo b_lo term is ~2^-16 of the product).  A BF16-stored input
+// has no low part, so only two products remain.
+// The factor is staged in LDS already split and packed: entry (r, lb, g) holds
+// F[4lb..4lb+3, k0 + 4g + r] as four bfloat16.
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+  bf2 v = {(__bf16)a, (__bf16)b};  // hardware round-to-nearest-even pack on gfx950
+  return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ float bf16_low_f32(uint32_t u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_high_f32(uint32_t u) { return __uint_as_float(u & 0xFFFF0000u); }
+__device__ __forceinline__ s4 as_s4(uint2 v) { return __builtin_bit_cast(s4, v); }
+__device__ __forceinline__ f4 mfma4x4x4bf16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+}
+// hi/lo packs of four consecutive reduction values
+__device__ __forceinline__ void split4(float x0, float x1, float x2, float x3, uint2& hi,
+                                      uint2& lo) {
+  hi.x = pack_bf16(x0, x1);
+  hi.y = pack_bf16(x2, x3);
+  lo.x = pack_bf16(x0 - bf16_low_f32(hi.x), x1 - bf16_high_f32(hi.x));
+  lo.y = pack_bf16(x2 - bf16_low_f32(hi.y), x3 - bf16_high_f32(hi.y));
+}
+
+template <int KG, bool X3>
+__device__ __forceinline__ void stage_factor_bf16(uint2* FH, uint2* FL,
+                                                  const float* __restrict__ F, int L, int LB,
+                                                  int Kt, int k0) {
+  const int total = 4 * LB * KG;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int g = e % KG;
+    const int t = e / KG;
+    const int lb = t % LB;
+    const int r = t / LB;
+    const int k = k0 + 4 * g + r;
+    float f[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int l = 4 * lb + q;
+      f[q] = (k < Kt && l < L) ? F[(int64_t)l * Kt + k] : 0.f;
+    }
+    uint2 hi, lo;
+    split4(f[0], f[1], f[2], f[3], hi, lo);
+    FH[e] = hi;
+    if (X3) FL[e] = lo;
+  }
+}
+
+// Wide path (B % 4 == 0): lane owns columns c0 + 4i .. c0 + 4i + 3.
+template <int KG, typename TIn, bool NT, bool X3>
+__global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
+                                                     const float* __restrict__ F,
+                                                     float* __restrict__ out, int64_t C, int L,
+                                                     int64_t B, int Kt) {
+  extern __shared__ uint2 sfb[];
+  const int LB = (L + 3) / 4;
+  uint2* FH = sfb;
+  uint2* FL = sfb + 4 * LB * KG;
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor_bf16<KG, X3>(FH, FL, F, L, LB, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
+  if (((int64_t)blockIdx.x * 4 + wave) * 256 >= C) return;
+  const bool active = c < C;
+  const int64_t a = active ? c / B : 0;
+  const int64_t b = active ? c - a * B : 0;
+  const TIn* p = in + (a * L) * B + b;
+  const uint2* fh = FH + (lane & 3) * LB * KG;
+  const uint2* fl = FL + (lane & 3) * LB * KG;
+  constexpr bool kSplitIn = X3 && std::is_same<TIn, float>::value;
+
+  f4 acc[KG][4];
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int U = 2;  // blocks of four rows per step: eight 16-byte loads in flight
+  for (int lb0 = 0; lb0 < LB; lb0 += U) {
+    f4 x[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = 4 * (lb0 + u) + q;
+        x[u][q] = (active && l < L) ? load4_f32<NT>(p + (int64_t)l * B)
+                                    : f4{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int lb = lb0 + u;
+      if (lb >= LB) break;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint2 bh, bl;
+        split4(x[u][0][j], x[u][1][j], x[u][2][j], x[u][3][j], bh, bl);
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          const uint2 ah = fh[lb * KG + g];
+          acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g][j]);
+          if (X3) {
+            acc[g][j] = mfma4x4x4bf16(as_s4(fl[lb * KG + g]), as_s4(bh), acc[g][j]);
+            if (kSplitIn) acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g][j]);
+          }
+        }
+      }
+    }
+  }
+  if (!active) return;
+  float* q = out + (a * Kt) * B + b;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) {
+        f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
+        *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
+      }
+    }
+}
+
+// Row path (B == 1, L % 4 == 0): lane owns row a; four consecutive l of its
+// row form one MFMA operand as loaded.
+template <int KG, typename TIn, bool NT, bool X3>
+__global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
+                                                     const float* __restrict__ F,
+                                                     float* __restrict__ out, int64_t A, int L,
+                                                     int Kt) {
+  extern __shared__ uint2 sfb[];
+  const int LB = L / 4;
+  uint2* FH = sfb;
+  uint2* FL = sfb + 4 * LB * KG;
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor_bf16<KG, X3>(FH, FL, F, L, LB, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wave_row0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+  if (wave_row0 >= A) return;
+  const int64_t a = wave_row0 + lane;
+  const bool active = a < A;
+  const TIn* p = in + (active ? a : 0) * L;
+  const uint2* fh = FH + (lane & 3) * LB * KG;
+  const uint2* fl = FL + (lane & 3) * LB * KG;
+  constexpr bool kSplitIn = X3 && std::is_same<TIn, float>::value;
+
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+  constexpr int U = 8;
+  for (int lb0 = 0; lb0 < LB; lb0 += U) {
+    f4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = (active && lb0 + u < LB) ? load4_f32<NT>(p + 4 * (lb0 + u)) : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int lb = lb0 + u;
+      if (lb >= LB) break;
+      uint2 bh, bl;
+      split4(x[u][0], x[u][1], x[u][2], x[u][3], bh, bl);
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        const uint2 ah = fh[lb * KG + g];
+        acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g]);
+        if (X3) {
+          acc[g] = mfma4x4x4bf16(as_s4(fl[lb * KG + g]), as_s4(bh), acc[g]);
+          if (kSplitIn) acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g]);
+        }
+      }
+    }
   }
   if (!active) return;
   float* q = out + a * Kt;
@@ -336,6 +534,49 @@ Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
   return Path::kTile;
 }
 
+// K-group instances compiled for the MFMA paths (KG groups of four outputs).
+constexpr int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
+
+int64_t grid_blocks(Path path, int64_t A, int64_t B) {
+  if (path == Path::kWide) return (A * B + 1023) / 1024;
+  if (path == Path::kRows) return (A + 255) / 256;
+  return 0;
+}
+
+// The smallest instance covering ceil(K/4) groups if it fits in `kg_cap`
+// (the groups whose factor slice fits in LDS), else the largest that fits
+// (K is then covered by several chunks).  Grids of fewer blocks than CUs
+// trade a larger KG for more K-chunks (more blocks; the input is re-read
+// from cache).
+int pick_kg(int64_t K, int kg_cap, int64_t blocks) {
+  const int need = (int)((K + 3) / 4);
+  int kg = 1;
+  for (int c : kInst)
+    if (c <= kg_cap) kg = c;  // largest fitting instance
+  for (int c : kInst)
+    if (c >= need && c <= kg_cap) {
+      kg = c;
+      break;
+    }
+  if (blocks > 0 && blocks < 256 && need > 1) {
+    // cut K into balanced chunks (2, 3, ... groups of ceil(need/chunks))
+    // until the grid covers the chip
+    for (int chunks = 2; chunks <= need; ++chunks) {
+      const int want = (need + chunks - 1) / chunks;
+      int pick = 0;
+      for (int c : kInst)
+        if (c >= want && c <= kg_cap) {
+          pick = c;
+          break;
+        }
+      if (pick == 0) break;
+      kg = pick;
+      if (blocks * ((need + kg - 1) / kg) >= 256) break;
+    }
+  }
+  return kg;
+}
+
 template <typename TIn, int KG, bool NT>
 hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
                          int K, float* out, hipStream_t st) {
@@ -383,45 +624,75 @@ hipError_t launch_f32_nt(Path path, int kg, const TIn* in, int64_t A, int L, int
 template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                       float* out, bool stream_in, hipStream_t st) {
-  // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path):
-  // the smallest instance covering ceil(K/4) groups if it fits, else the
-  // largest that fits (K is then covered by several chunks).  Small grids
-  // trade a larger KG for more K-chunks (more blocks; the input is re-read
-  // from cache).
-  static const int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
-  const int need = (K + 3) / 4;
-  const int kg_cap = std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L));
-  int kg = 1;
-  for (int c : kInst)
-    if (c <= kg_cap) kg = c;  // largest fitting instance
-  for (int c : kInst)
-    if (c >= need && c <= kg_cap) {
-      kg = c;
-      break;
-    }
+  // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
   const Path path = choose_path(in, out, L, B);
-  int64_t blocks = 0;
-  if (path == Path::kWide) blocks = (A * B + 1023) / 1024;
-  else if (path == Path::kRows) blocks = (A + 255) / 256;
-  if (blocks > 0 && blocks < 256 && need > 1) {
-    // fewer blocks than CUs: cut K into balanced chunks (2, 3, ... groups of
-    // ceil(need/chunks)) until the grid covers the chip
-    for (int chunks = 2; chunks <= need; ++chunks) {
-      const int want = (need + chunks - 1) / chunks;
-      int pick = 0;
-      for (int c : kInst)
-        if (c >= want && c <= kg_cap) {
-          pick = c;
-          break;
-        }
-      if (pick == 0) break;
-      kg = pick;
-      if (blocks * ((need + kg - 1) / kg) >= 256) break;
-    }
-  }
+  const int kg = pick_kg(K, std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L)),
+                         grid_blocks(path, A, B));
   if (stream_in)
     return launch_f32_nt<TIn, true>(path, kg, in, A, L, B, F, K, out, st);
   return launch_f32_nt<TIn, false>(path, kg, in, A, L, B, F, K, out, st);
+}
+
+// 16 groups x 4 columns of accumulators exceed the register file of the BF16
+// wide kernel (it spills); wider K is covered by more chunks.
+constexpr int kWideBf16MaxKG = 12;
+
+template <typename TIn, int KG, bool NT, bool X3>
+hipError_t launch_bf16_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
+                          int K, float* out, hipStream_t st) {
+  const int chunks = (K + 4 * KG - 1) / (4 * KG);
+  const size_t lds = (size_t)32 * ((L + 3) / 4) * KG * (X3 ? 2 : 1);
+  if (path == Path::kWide) {
+    if constexpr (KG <= kWideBf16MaxKG) {
+      const int64_t C = A * B;
+      dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
+      hipLaunchKernelGGL((ttm_wide_bf16<KG, TIn, NT, X3>), grid, dim3(256), lds, st, in, F, out,
+                         C, L, B, K);
+    } else {
+      return hipErrorInvalidValue;  // not reached: launch_bf16 caps the wide KG
+    }
+  } else {
+    dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_rows_bf16<KG, TIn, NT, X3>), grid, dim3(256), lds, st, in, F, out,
+                       A, L, K);
+  }
+  return hipGetLastError();
+}
+
+template <typename TIn, bool NT, bool X3>
+hipError_t launch_bf16_nt(Path path, int kg, const TIn* in, int64_t A, int L, int64_t B,
+                          const float* F, int K, float* out, hipStream_t st) {
+  switch (kg) {
+    case 1: return launch_bf16_kg<TIn, 1, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 2: return launch_bf16_kg<TIn, 2, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 3: return launch_bf16_kg<TIn, 3, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 4: return launch_bf16_kg<TIn, 4, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 5: return launch_bf16_kg<TIn, 5, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 6: return launch_bf16_kg<TIn, 6, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 8: return launch_bf16_kg<TIn, 8, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 12: return launch_bf16_kg<TIn, 12, NT, X3>(path, in, A, L, B, F, K, out, st);
+    default: return launch_bf16_kg<TIn, 16, NT, X3>(path, in, A, L, B, F, K, out, st);
+  }
+}
+
+// BF16 / split-BF16 compute.  Nodes that need the tile path (B not a multiple
+// of four, or B == 1 with L not a multiple of four) run the FP32 tile kernel:
+// at least as accurate as the mode asks for.
+template <typename TIn>
+hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
+                       float* out, bool stream_in, bool x3, hipStream_t st) {
+  const Path path = choose_path(in, out, L, B);
+  if (path == Path::kTile) return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, st);
+  const int per_group = 32 * ((L + 3) / 4) * (x3 ? 2 : 1);  // LDS bytes per K-group
+  int kg_cap = std::max(1, kLdsBudget / per_group);
+  if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
+  const int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
+  if (stream_in) {
+    if (x3) return launch_bf16_nt<TIn, true, true>(path, kg, in, A, L, B, F, K, out, st);
+    return launch_bf16_nt<TIn, true, false>(path, kg, in, A, L, B, F, K, out, st);
+  }
+  if (x3) return launch_bf16_nt<TIn, false, true>(path, kg, in, A, L, B, F, K, out, st);
+  return launch_bf16_nt<TIn, false, false>(path, kg, in, A, L, B, F, K, out, st);
 }
 
 template <int KC>
@@ -458,6 +729,14 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
                                (double*)out, st);
     return launch_f64_kc<32>((const double*)in, A, Li, B, (const double*)F, (int)K,
                              (double*)out, st);
+  }
+  if (compute == TK_C_BF16 || compute == TK_C_BF16X3) {
+    const bool x3 = compute == TK_C_BF16X3;
+    if (in_dtype == TK_F32)
+      return launch_bf16<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
+                                (float*)out, stream_in, x3, st);
+    return launch_bf16<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
+                                 (float*)out, stream_in, x3, st);
   }
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,

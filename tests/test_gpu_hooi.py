@@ -68,6 +68,15 @@ CASES = [
     ((16, 12, 10, 8, 6, 4), (4, 4, 3, 3, 2, 2), "f32", "fp32", 1e-5),
     ((20, 20, 20, 20, 20), (4, 4, 4, 4, 4), "bf16", "fp32", 1e-5),
     ((40, 33, 17), (6, 5, 7), "f64", "fp64", 1e-10),
+    # reduced precision, bounds per leaf against the exact chain: bf16x3 1e-4;
+    # BF16 1.5e-2 for up to five rounded TTMs on the path to a leaf
+    ((24, 20, 16, 12), (4, 5, 3, 6), "f32", "bf16x3", 1e-4),
+    ((12, 11, 10, 9, 8), (3, 3, 2, 2, 4), "f32", "bf16", 1.5e-2),
+    ((16, 12, 10, 8, 6, 4), (4, 4, 3, 3, 2, 2), "f32", "bf16", 1.5e-2),
+    ((20, 20, 20, 20, 20), (4, 4, 4, 4, 4), "bf16", "bf16", 1.5e-2),
+    ((20, 20, 20, 20, 20), (4, 4, 4, 4, 4), "bf16", "bf16x3", 1e-4),
+    ((64, 48, 40, 32), (8, 12, 4, 16), "f32", "bf16", 1.5e-2),
+    ((64, 48, 40, 32), (8, 12, 4, 16), "f32", "bf16x3", 1e-4),
 ]
 
 
@@ -79,7 +88,7 @@ def test_tree_leaves_equal_naive_chain(L, K, dtype, compute, tol, kind):
     T64 = O.as_f64(T, dtype)
     g = np.random.default_rng(17)
     F = [np.linalg.qr(g.standard_normal((L[n], K[n])))[0] for n in range(len(L))]
-    if compute == "fp32":
+    if compute != "fp64":
         F = [f.astype(np.float32).astype(np.float64) for f in F]  # both sides see the same F
     ctx = tk.hooi_init(_device_T(T, dtype), K, compute=compute, F0=F,
                        plan=tk.ttm_tree_plan(L, K, kind))
@@ -109,6 +118,28 @@ def test_fp32_iterations_match_oracle():
     for n in range(4):
         assert subspace_dist(ctx.factor(n), Fo[n]) < 1e-4
     assert abs(ctx.error_explicit() - errs_o[-1]) < 1e-3 * errs_o[-1]
+
+
+@pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
+def test_reduced_precision_iterations_match_oracle(compute):
+    """BF16-stored planted tensor (five modes), HOOI in BF16 / bf16x3 against
+    the FP64 oracle on the same stored values.  The error is stationary in
+    the factors, so factor perturbations enter it to second order: the
+    relative error of the Tucker error is bounded by 1e-3."""
+    L, K = (24, 24, 24, 24, 24), (4, 4, 4, 4, 4)
+    T, _ = synth.planted(L, K, noise=1e-2, noise_kind="rel", dtype="bf16", cfg=72)
+    T64 = O.as_f64(T, "bf16")
+    print(f"bf16 storage, {compute} HOOI 24^5", flush=True)
+    ctx = tk.hooi_init(_device_T(T, "bf16"), K, compute=compute)
+    errs = ctx.iterate(3)
+    Fo, Go, errs_o = O.hooi(T64, K, 3)
+    print(f"errors gpu {errs} oracle {errs_o}", flush=True)
+    dists = [subspace_dist(ctx.factor(n), Fo[n]) for n in range(5)]
+    print(f"subspace distances {dists}", flush=True)
+    for e, eo in zip(errs, errs_o):
+        assert abs(e - eo) < 1e-3 * eo
+    assert abs(ctx.error_explicit() - errs_o[-1]) < 1e-3 * errs_o[-1]
+    assert max(dists) < (1e-1 if compute == "bf16" else 1e-3)
 
 
 def test_checkpoint_resume_is_exact_and_runs_are_deterministic():

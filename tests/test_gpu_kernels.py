@@ -9,6 +9,7 @@ import pytest
 
 import synth
 from oracle import hooi as O
+from oracle import precision as P
 from tests.gpu_util import rel_err, subspace_dist, to_dev, torch_dev
 
 pytestmark = pytest.mark.gpu
@@ -63,6 +64,52 @@ def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch.cuda.synchronize()
     ref = O.ttm(O.as_f64(Xb, "bf16"), F.astype(np.float64).T, 1)
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
+
+
+def _bf16_mfma_path(L, B):
+    """Nodes the BF16 kernels take (others run the FP32 tile kernel)."""
+    return (B % 4 == 0 and B >= 16) or (B == 1 and L % 4 == 0)
+
+
+# Reduced precision.  On the BF16 kernels every product of two bfloat16 values
+# is exact in FP32, so the result equals the float64 model of the mode
+# (oracle.precision) up to FP32 accumulation: 1e-5.  Against the exact
+# product the stated bounds are 1.5e-2 (BF16: one rounding of each operand,
+# 2^-8 relative) and 1e-4 (bf16x3: 2^-16 representation error per operand).
+BF16_BOUND = {"bf16": 1.5e-2, "bf16x3": 1e-4}
+
+
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES + [(2, 64, 4096, 48), (4, 2048, 16, 5),
+                                                 (300, 400, 1, 44)])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
+def test_ttm_reduced_precision(A, L, B, K, storage, compute):
+    torch, dev = torch_dev()
+    print(f"ttm {storage}/{compute} A={A} L={L} B={B} K={K}", flush=True)
+    g = np.random.default_rng(23 + A + 3 * L + 5 * B + 7 * K)
+    X = g.standard_normal((A, L, B)).astype(np.float32)
+    F = g.standard_normal((L, K)).astype(np.float32)
+    if storage == "bf16":
+        Xb = synth.round_to_bf16_bits(X)
+        xt = torch.from_numpy(Xb.view(np.int16)).view(torch.bfloat16).to(dev)
+        X64 = O.as_f64(Xb, "bf16")
+    else:
+        xt = to_dev(X)
+        X64 = X.astype(np.float64)
+    out = torch.full((A, K, B), float("nan"), dtype=torch.float32, device=dev)
+    tk.ttm(xt, A, L, B, to_dev(F), K, out, compute=compute)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    exact = O.ttm(X64, F.astype(np.float64).T, 1)
+    if _bf16_mfma_path(L, B):
+        if compute == "bf16":
+            model = P.ttm_bf16(X64, F.T, 1)
+        else:
+            model = P.ttm_bf16x3(X64, F.T, 1, x_is_bf16=storage == "bf16")
+        assert rel_err(got, model) < 1e-5
+    else:
+        assert rel_err(got, exact) < 1e-5
+    assert rel_err(got, exact) < BF16_BOUND[compute]
 
 
 @pytest.mark.parametrize("A,L,B,K", [(3, 37, 100, 5), (100, 64, 1, 8), (7, 20, 9, 20),
