@@ -72,6 +72,8 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
   const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
   if (((int64_t)blockIdx.x * 4 + wave) * 256 >= C) return;  // whole wave idle
   const bool active = c < C;
+  // lanes past the end read row a = 0 (always in bounds) and store nothing:
+  // the loads stay unconditional, so they are issued back to back
   const int64_t a = active ? c / B : 0;
   const int64_t b = active ? c - a * B : 0;
   const TIn* p = in + (a * L) * B + b;
@@ -89,7 +91,9 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
     f4 x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      x[u] = active ? load4_f32<NT>(p + (int64_t)(l + u) * B) : f4{0.f, 0.f, 0.f, 0.f};
+      x[u] = load4_f32<NT>(p + (int64_t)(l + u) * B);
+    // keep the batch of loads together ahead of the MFMAs that consume them
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
     }
   }
   for (; l < L; ++l) {
-    const f4 x = active ? load4_f32<NT>(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
+    const f4 x = load4_f32<NT>(p + (int64_t)l * B);
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
       const float fa = ft[l * KG + g];
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
   if (wave_row0 >= A) return;  // whole wave idle
   const int64_t a = wave_row0 + lane;
   const bool active = a < A;
-  const TIn* p = in + (active ? a : 0) * L;
+  const TIn* p = in + (active ? a : 0) * L;  // lanes past the end re-read row 0
   const float* ft = smem + (lane & 3) * L * KG;
 
   f4 acc[KG];
@@ -157,7 +161,8 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
     f4 x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      x[u] = active ? load4_f32<NT>(p + l + 4 * u) : f4{0.f, 0.f, 0.f, 0.f};
+      x[u] = load4_f32<NT>(p + l + 4 * u);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
           acc[g] = mfma4x4x1(ft[(l + 4 * u + j) * KG + g], x[u][j], acc[g]);
   }
   for (; l < L; l += 4) {
-    const f4 x = active ? load4_f32<NT>(p + l) : f4{0.f, 0.f, 0.f, 0.f};
+    const f4 x = load4_f32<NT>(p + l);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -243,6 +248,27 @@ __device__ __forceinline__ void stage_factor_bf16(uint2* FH, uint2* FL,
   }
 }
 
+// One block of four rows x[q] (q = l mod 4) of the lane's four columns:
+// column j's operand is the four values x[0..3][j].
+template <int KG, bool X3, bool kSplitIn>
+__device__ __forceinline__ void wide_bf16_block(f4 (&acc)[KG][4], const f4 (&x)[4],
+                                                const uint2* fh, const uint2* fl) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint2 bh, bl;
+    split4(x[0][j], x[1][j], x[2][j], x[3][j], bh, bl);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const uint2 ah = fh[g];
+      acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g][j]);
+      if (X3) {
+        acc[g][j] = mfma4x4x4bf16(as_s4(fl[g]), as_s4(bh), acc[g][j]);
+        if (kSplitIn) acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g][j]);
+      }
+    }
+  }
+}
+
 // Wide path (B % 4 == 0): lane owns columns c0 + 4i .. c0 + 4i + 3.
 template <int KG, typename TIn, bool NT, bool X3>
 __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
@@ -274,36 +300,29 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-  constexpr int U = 2;  // blocks of four rows per step: eight 16-byte loads in flight
-  for (int lb0 = 0; lb0 < LB; lb0 += U) {
+  // blocks of four rows per step: 8 (FP32 input) or 16 (BF16 input) loads in flight
+  constexpr int U = (sizeof(TIn) == 2 && KG <= 8) ? 4 : 2;
+  const int LF = L / 4;  // blocks with all four rows inside L
+  int lb = 0;
+  for (; lb + U <= LF; lb += U) {
     f4 x[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = 4 * (lb0 + u) + q;
-        x[u][q] = (active && l < L) ? load4_f32<NT>(p + (int64_t)l * B)
-                                    : f4{0.f, 0.f, 0.f, 0.f};
-      }
+      for (int q = 0; q < 4; ++q) x[u][q] = load4_f32<NT>(p + (int64_t)(4 * (lb + u) + q) * B);
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int lb = lb0 + u;
-      if (lb >= LB) break;
+    for (int u = 0; u < U; ++u)
+      wide_bf16_block<KG, X3, kSplitIn>(acc, x[u], fh + (lb + u) * KG, fl + (lb + u) * KG);
+  }
+  for (; lb < LB; ++lb) {  // remaining blocks, the last one possibly ragged
+    f4 x[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        uint2 bh, bl;
-        split4(x[u][0][j], x[u][1][j], x[u][2][j], x[u][3][j], bh, bl);
-#pragma unroll
-        for (int g = 0; g < KG; ++g) {
-          const uint2 ah = fh[lb * KG + g];
-          acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g][j]);
-          if (X3) {
-            acc[g][j] = mfma4x4x4bf16(as_s4(fl[lb * KG + g]), as_s4(bh), acc[g][j]);
-            if (kSplitIn) acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g][j]);
-          }
-        }
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int l = 4 * lb + q;
+      x[q] = l < L ? load4_f32<NT>(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
     }
+    wide_bf16_block<KG, X3, kSplitIn>(acc, x, fh + lb * KG, fl + lb * KG);
   }
   if (!active) return;
   float* q = out + (a * Kt) * B + b;
@@ -317,6 +336,22 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
         *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
       }
     }
+}
+
+template <int KG, bool X3, bool kSplitIn>
+__device__ __forceinline__ void rows_bf16_block(f4 (&acc)[KG], const f4 x, const uint2* fh,
+                                                const uint2* fl) {
+  uint2 bh, bl;
+  split4(x[0], x[1], x[2], x[3], bh, bl);
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    const uint2 ah = fh[g];
+    acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g]);
+    if (X3) {
+      acc[g] = mfma4x4x4bf16(as_s4(fl[g]), as_s4(bh), acc[g]);
+      if (kSplitIn) acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g]);
+    }
+  }
 }
 
 // Row path (B == 1, L % 4 == 0): lane owns row a; four consecutive l of its
@@ -338,7 +373,7 @@ __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
   if (wave_row0 >= A) return;
   const int64_t a = wave_row0 + lane;
   const bool active = a < A;
-  const TIn* p = in + (active ? a : 0) * L;
+  const TIn* p = in + (active ? a : 0) * L;  // lanes past the end re-read row 0
   const uint2* fh = FH + (lane & 3) * LB * KG;
   const uint2* fl = FL + (lane & 3) * LB * KG;
   constexpr bool kSplitIn = X3 && std::is_same<TIn, float>::value;
@@ -348,28 +383,18 @@ __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
   for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
 
   constexpr int U = 8;
-  for (int lb0 = 0; lb0 < LB; lb0 += U) {
+  int lb = 0;
+  for (; lb + U <= LB; lb += U) {
     f4 x[U];
 #pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = load4_f32<NT>(p + 4 * (lb + u));
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
     for (int u = 0; u < U; ++u)
-      x[u] = (active && lb0 + u < LB) ? load4_f32<NT>(p + 4 * (lb0 + u)) : f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int lb = lb0 + u;
-      if (lb >= LB) break;
-      uint2 bh, bl;
-      split4(x[u][0], x[u][1], x[u][2], x[u][3], bh, bl);
-#pragma unroll
-      for (int g = 0; g < KG; ++g) {
-        const uint2 ah = fh[lb * KG + g];
-        acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bh), acc[g]);
-        if (X3) {
-          acc[g] = mfma4x4x4bf16(as_s4(fl[lb * KG + g]), as_s4(bh), acc[g]);
-          if (kSplitIn) acc[g] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g]);
-        }
-      }
-    }
+      rows_bf16_block<KG, X3, kSplitIn>(acc, x[u], fh + (lb + u) * KG, fl + (lb + u) * KG);
   }
+  for (; lb < LB; ++lb)
+    rows_bf16_block<KG, X3, kSplitIn>(acc, load4_f32<NT>(p + 4 * lb), fh + lb * KG, fl + lb * KG);
   if (!active) return;
   float* q = out + a * Kt;
 #pragma unroll
