@@ -9,7 +9,10 @@ direct core chain (the error of the last step) is included.
 Prints ONE JSON line.  Extra objects:
   roofline     -- the dominant kernel (the root-level TTMs that read T), timed
                   with HIP events on the library's stream; algorithmic bytes
-                  = 4 * (|In| + |Out|) + factor per launch, HBM peak 8 TB/s.
+                  = 4 * (|In| + |Out|) + factor per launch, HBM peak 8 TB/s;
+                  traffic = measured HBM bytes per launch from the committed
+                  counter summary under profiles/ (null once the kernel
+                  sources differ from those the counters were taken with).
   cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
                   host for a bounded sample: one HOOI invocation of the same
                   tensor.
@@ -39,6 +42,38 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "ttm_wide_f32_root_c2_hbm_counters.txt")
+
+
+def recorded_traffic():
+    """HBM bytes per root-TTM launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read().splitlines()
+    except OSError:
+        return None
+    traffic, digest, files = None, None, []
+    for line in text:
+        line = line.strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = int(line.split(":")[1])
+        elif line.startswith("kernel_source_sha256_16:"):
+            parts = line.split(":", 1)[1].split()
+            digest = parts[0]
+            files = [f.strip("()") for f in parts[1:]]
+    if traffic is None or digest is None or not files:
+        return None
+    h = hashlib.sha256()
+    for f in files:
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    return traffic if h.hexdigest()[:16] == digest else None
+
+
 def root_ttm_roofline(ctx, plan, reps=3):
     """Average duration of the root-level TTM launches (HIP events, ctx stream)."""
     nodes = plan.nodes()
@@ -56,7 +91,7 @@ def root_ttm_roofline(ctx, plan, reps=3):
     bytes_per_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(),
                 kernel="ttm_wide_f32 (root nodes, reads T)", launches=len(times),
                 avg_ms=round(avg_ms, 4), bytes_per_launch=int(bytes_per_launch)), ms
 
@@ -88,6 +123,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="finish with three device-to-device copies of BYTES bytes "
+                         "(reference dispatches for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -188,6 +226,15 @@ def main():
     if not args.skip_cpu_baseline:
         log("timing the FP64 oracle on one HOOI invocation ...")
         out["cpu_baseline"] = cpu_baseline(T, K, F0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 4 * n
+        del src, dst
     print(json.dumps(out), flush=True)
 
 
