@@ -28,6 +28,9 @@ COMMON = [
     "-Wno-unused-result",
     # keep the compiler from forming packed FP32 arithmetic on gfx950
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in VGPRs: the AGPR form made the allocator rotate the
+    # TTM accumulators through copies on every loop iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(os.path.dirname(HERE), "include"),
 ]
 

@@ -129,6 +129,15 @@ struct tk_ctx {
   // stream waits on ev_fac[n] only before it next uses factor n, so a solve
   // overlaps the rest of its own tree pass and the start of the next one.
   hipStream_t side = nullptr;
+  // Device work runs on `st`.  With CU partitioning (the default) `st` is an
+  // internal stream masked away from a few CUs that only the side stream
+  // uses, so the latency-bound eigensolver never shares a CU with the
+  // bandwidth-bound tree kernels; `user` is then the caller's stream, joined
+  // to `st` by events at every entry point (enter/leave).
+  hipStream_t user = nullptr;
+  bool own_main = false;
+  int side_cus = 0;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_leaf[TK_MAX_MODES] = {};
   hipEvent_t ev_fac[TK_MAX_MODES] = {};
   bool pending[TK_MAX_MODES] = {};
@@ -136,6 +145,7 @@ struct tk_ctx {
 
   ~tk_ctx() {
     if (side) (void)hipStreamSynchronize(side);
+    if (own_main) (void)hipStreamSynchronize(st);
     void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc,
                     wdtype == TK_F64 ? nullptr : Fcb, S, ev, eigwork, status, jobs,
                     jobs_cold, gpart, rpart, scal, core};
@@ -148,6 +158,9 @@ struct tk_ctx {
     for (hipEvent_t e : ev_fac)
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
+    if (own_main) (void)hipStreamDestroy(st);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
   }
 
   const void* fc(int n) const {
@@ -157,6 +170,74 @@ struct tk_ctx {
 };
 
 namespace {
+
+// Order the context's stream after the caller's work on entry and the
+// caller's stream after the context's work on exit (no-ops without an
+// internal stream).
+struct Handoff {
+  tk_ctx* c;
+  explicit Handoff(tk_ctx* ctx) : c(ctx) {
+    if (c && c->own_main) {
+      (void)hipEventRecord(c->ev_in, c->user);
+      (void)hipStreamWaitEvent(c->st, c->ev_in, 0);
+    }
+  }
+  ~Handoff() {
+    if (c && c->own_main) {
+      (void)hipEventRecord(c->ev_out, c->st);
+      (void)hipStreamWaitEvent(c->user, c->ev_out, 0);
+    }
+  }
+};
+
+// CUs reserved for the side stream: TK_SIDE_CUS (0 disables the partition),
+// default 8.  Mask bit i names the runtime's CU i; the first eight cover one
+// CU of each of the eight XCDs (measured: with 1-4 reserved bits the solves
+// still ran 3x slower under a concurrent root TTM, with 8 they did not).
+int reserved_side_cus() {
+  const char* v = getenv("TK_SIDE_CUS");
+  if (!v || !*v) return 8;
+  const int n = atoi(v);
+  return n < 0 ? 0 : std::min(n, 64);
+}
+
+// Create the side stream and, when CU partitioning is available, the
+// internal main stream; on any failure of the masked variant fall back to
+// one unmasked side stream and the caller's stream.
+hipError_t create_streams(tk_ctx* c) {
+  const int reserve = reserved_side_cus();
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (reserve > 0 && ncu > 4 * reserve) {
+    const int words = (ncu + 31) / 32;
+    std::vector<uint32_t> side_mask(words, 0u), main_mask(words, 0u);
+    for (int i = 0; i < ncu; ++i) (i < reserve ? side_mask : main_mask)[i / 32] |= 1u << (i % 32);
+    hipStream_t side = nullptr, main = nullptr;
+    hipError_t e1 = hipExtStreamCreateWithCUMask(&side, (uint32_t)words, side_mask.data());
+    hipError_t e2 = e1 == hipSuccess
+                        ? hipExtStreamCreateWithCUMask(&main, (uint32_t)words, main_mask.data())
+                        : e1;
+    hipError_t e3 = e2 == hipSuccess ? hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) : e2;
+    hipError_t e4 = e3 == hipSuccess ? hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) : e3;
+    if (e4 == hipSuccess) {
+      c->side = side;
+      c->user = c->st;
+      c->st = main;
+      c->own_main = true;
+      c->side_cus = reserve;
+      return hipSuccess;
+    }
+    if (side) (void)hipStreamDestroy(side);
+    if (main) (void)hipStreamDestroy(main);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    c->ev_in = c->ev_out = nullptr;
+    (void)hipGetLastError();
+  }
+  return hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+}
 
 int run_eig(tk_ctx* c, bool warm, double* F_out, int maxit) {
   TK_HIP(launch_eig(c->s.N, warm ? c->jobs : c->jobs_cold, 0, c->Lmax, c->pmax, c->S, c->F64a,
@@ -436,7 +517,12 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     if (j.p != j.L) j.p = std::max(j.K, std::min(j.p, j.K + 4));
   }
   {
-    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    hipError_t e = create_streams(c);
+    if (e == hipSuccess && c->own_main) {
+      // the caller's stream may still be producing T
+      e = hipEventRecord(c->ev_in, c->user);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->st, c->ev_in, 0);
+    }
     for (int n = 0; n < N && e == hipSuccess; ++n) {
       e = hipEventCreateWithFlags(&c->ev_leaf[n], hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fac[n], hipEventDisableTiming);
@@ -548,6 +634,7 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
 extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
   clear_error();
   if (!c) return fail(TK_EINVAL, "ctx is null");
+  Handoff handoff(c);
   if (iters < 1) return fail(TK_EINVAL, "iters=%d < 1", iters);
   if (int rc = ensure_scal(c, iters + 2)) return rc;
   // scal[0] = ||T||^2 (kept), scal[1 + t] = ||G^(t)||^2, t = 0..iters
@@ -571,6 +658,7 @@ extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
 extern "C" int tucker_error(tk_ctx* c, double* rel_err, double* normT, double* normG) {
   clear_error();
   if (!c) return fail(TK_EINVAL, "ctx is null");
+  Handoff handoff(c);
   if (int rc = join_factors(c)) return rc;
   if (!c->core_valid) {
     if (int rc = core_chain(c, 1)) return rc;
@@ -589,6 +677,7 @@ extern "C" int tucker_error(tk_ctx* c, double* rel_err, double* normT, double* n
 extern "C" int tucker_error_explicit(tk_ctx* c, double* rel_err) {
   clear_error();
   if (!c || !rel_err) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   if (int rc = tucker_error(c, nullptr, nullptr, nullptr)) return rc;
   const Shape& s = c->s;
   const int N = s.N;
@@ -664,6 +753,7 @@ extern "C" int tucker_error_explicit(tk_ctx* c, double* rel_err) {
 extern "C" int tk_get_factor(tk_ctx* c, int n, double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
   if (int rc = join_factors(c)) return rc;
   TK_HIP(hipMemcpyAsync(host, c->F64a + c->fofs[n], sizeof(double) * (c->fofs[n + 1] - c->fofs[n]),
@@ -675,6 +765,7 @@ extern "C" int tk_get_factor(tk_ctx* c, int n, double* host) {
 extern "C" int tk_get_core(tk_ctx* c, double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   if (int rc = tucker_error(c, nullptr, nullptr, nullptr)) return rc;
   if (c->wdtype == TK_F64) {
     TK_HIP(hipMemcpyAsync(host, c->core, sizeof(double) * c->core_elems, hipMemcpyDeviceToHost, c->st));
@@ -692,6 +783,7 @@ extern "C" int tk_get_core(tk_ctx* c, double* host) {
 extern "C" int tk_set_factors(tk_ctx* c, const double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   for (size_t i = 0; i < c->fofs[c->s.N]; ++i)
     if (!std::isfinite(host[i])) return fail(TK_ENUMERIC, "factors hold NaN/Inf");
   if (int rc = join_factors(c)) return rc;
@@ -705,6 +797,7 @@ extern "C" int tk_set_factors(tk_ctx* c, const double* host) {
 extern "C" int tk_tree_pass(tk_ctx* c) {
   clear_error();
   if (!c) return fail(TK_EINVAL, "ctx is null");
+  Handoff handoff(c);
   const Shape& s = c->s;
   if (c->leaves.empty()) {
     c->leaves.assign(s.N, nullptr);
@@ -723,6 +816,7 @@ extern "C" int tk_tree_pass(tk_ctx* c) {
 extern "C" int tk_get_leaf(tk_ctx* c, int n, double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
   if (c->leaves.empty()) return fail(TK_EINVAL, "call tk_tree_pass first");
   const int64_t m = c->leaf_elems[n];
@@ -752,6 +846,7 @@ extern "C" int tk_get_leaf(tk_ctx* c, int n, double* host) {
 extern "C" int tk_get_gram(tk_ctx* c, int n, double* host) {
   clear_error();
   if (!c || !host) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
   TK_HIP(hipMemcpyAsync(host, c->S + c->sofs[n], sizeof(double) * (c->sofs[n + 1] - c->sofs[n]),
                         hipMemcpyDeviceToHost, c->st));
@@ -762,6 +857,7 @@ extern "C" int tk_get_gram(tk_ctx* c, int n, double* host) {
 extern "C" int tk_profile_tree(tk_ctx* c, float* ms_out, int cap, int* n) {
   clear_error();
   if (!c || !n) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   const size_t nn = c->tree.nodes.size();
   *n = (int)nn;
   if (!ms_out) return TK_OK;
@@ -786,6 +882,7 @@ extern "C" int tk_profile_tree(tk_ctx* c, float* ms_out, int cap, int* n) {
 extern "C" int tk_eig_iterations(tk_ctx* c, int* out) {
   clear_error();
   if (!c || !out) return fail(TK_EINVAL, "null argument");
+  Handoff handoff(c);
   TK_HIP(hipMemcpyAsync(out, c->status + c->s.N, sizeof(int) * c->s.N, hipMemcpyDeviceToHost,
                         c->st));
   TK_HIP(hipStreamSynchronize(c->st));
