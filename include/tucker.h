@@ -62,6 +62,18 @@ extern "C" {
 #define TK_C_BF16 2   /* BF16 operands on BF16 MFMA, FP32 accumulation            */
 #define TK_C_BF16X3 3 /* split BF16: a*b ~ ah*bh + ah*bl + al*bh, FP32 accumulation */
 
+/* TTM kernel choice for one node (FP32 / BF16 / bf16x3 compute):
+ * AUTO   -- by shape: the wide path (B % 4 == 0, B >= 16), the row path
+ *           (B == 1, L % 4 == 0), else the LDS-staged tile path; the K-group
+ *           count from the factor's LDS footprint and the grid size;
+ * STAGED -- always the LDS-staged tile path;
+ * SPLITK -- AUTO's path with half the K-groups per block (more blocks, the
+ *           input re-read from cache). */
+#define TK_TILE_AUTO 0
+#define TK_TILE_STAGED 1
+#define TK_TILE_SPLITK 2
+#define TK_TILE_COUNT 3
+
 /* tree kinds (Sec. 3.2 prior schemes, Sec. 3.3 optimal tree) */
 #define TK_TREE_DP 0        /* minimum multiply-add tree, dynamic program         */
 #define TK_TREE_CHAIN 1     /* N independent chains, ascending modes (naive)      */
@@ -175,6 +187,59 @@ int tk_profile_tree(tk_ctx* ctx, float* ms_out, int cap, int* n);
 int tk_eig_iterations(tk_ctx* ctx, int* out);
 
 void hooi_free(tk_ctx* ctx);
+
+/* ---- learned tree and kernel selection ------------------------------------ */
+
+/* Features of one TTM node for the cost model (TK_FEATURES floats):
+ * log2 A, log2 L, log2 B, log2 K, log2 input bytes, log2 output bytes,
+ * wide kernel applies (0/1), row kernel applies (0/1), input bytes per
+ * element / 4, compute class (FP32 0, BF16 0.5, bf16x3 1, FP64 2),
+ * tile == STAGED (0/1), tile == SPLITK (0/1). */
+#define TK_FEATURES 12
+int tk_ttm_features(int64_t A, int64_t L, int64_t B, int64_t K, int in_dtype, int compute,
+                    int tile, float* out);
+
+/* Average time (ms, HIP events on `stream`) of `reps` launches of the TTM
+ * node kernel chosen by `tile`, after one untimed launch.  Device buffers as
+ * for tk_ttm; their contents only need to be finite. */
+int tk_time_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
+                const void* F, int64_t K, void* out, int tile, int reps, void* stream,
+                float* ms);
+
+/* Per-node kernel choices of tree `rank` (n = its node count; leaf entries
+ * are ignored).  hooi_init uses the choices of the selected tree. */
+int tk_plan_set_tiles(tk_plan* plan, int rank, const int* tiles, int n);
+int tk_plan_get_tiles(const tk_plan* plan, int rank, int* tiles, int cap, int* n);
+
+/* MLP cost model, FP32 on the device: x' = (x - mu)/sigma,
+ * h1 = relu(W1 x' + b1), h2 = relu(W2 h1 + b2), y = w3.h2 + b3 (y: log of
+ * the node's time in ms).  Parameters flat in the order W1 (hidden x in_dim,
+ * row-major), b1, W2 (hidden x hidden), b2, w3, b3; the caller supplies the
+ * initial values (tk_mlp_param_count of them), so the library draws no random
+ * numbers.  Training: full-batch Adam (beta 0.9 / 0.999, eps 1e-8) on the
+ * mean squared error.  Host arrays in and out; errors TK_EINVAL / TK_ENOMEM /
+ * TK_EDEVICE. */
+typedef struct tk_mlp tk_mlp;
+int64_t tk_mlp_param_count(int in_dim, int hidden);
+int tk_mlp_create(int in_dim, int hidden, const float* params_host, tk_mlp** out);
+int tk_mlp_set_norm(tk_mlp* m, const float* mu, const float* sigma);
+int tk_mlp_get_params(const tk_mlp* m, float* host);
+int tk_mlp_set_params(tk_mlp* m, const float* host); /* also resets Adam's moments */
+int tk_mlp_forward(tk_mlp* m, const float* X_host, int n, float* y_host);
+int tk_mlp_loss_grad(tk_mlp* m, const float* X_host, const float* y_host, int n,
+                     float* loss_host, float* grad_host);
+int tk_mlp_train(tk_mlp* m, const float* X_host, const float* y_host, int n, int steps,
+                 float lr, float* loss_host /* steps values or NULL */);
+void tk_mlp_free(tk_mlp* m);
+
+/* Choose among the trees a TK_TREE_DP plan holds (topk > 1) and each
+ * internal node's kernel by the model's predicted time (sum over internal
+ * nodes, each at its fastest predicted kernel).  The choice replaces the DP
+ * optimum with automatic kernels only when predicted faster by more than
+ * `margin` (fraction); it is stored as the plan's selected rank and tiles.
+ * predicted_ms: NULL or tk_plan_count entries (each tree at its best kernels). */
+int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute, double margin,
+                    int* chosen, double* predicted_ms);
 
 /* ---- kernel-level entry points (device pointers, enqueued on `stream`) ---- */
 

@@ -13,6 +13,8 @@ Distributed Tucker Decomposition for Dense Tensors", arXiv 1707.05594):
   ``brute_plan.c``) used to pin the dynamic program.
 * ``oracle.precision`` -- exact float64 models of the BF16 and split-BF16
   (bf16x3) TTM node: operand rounding to bfloat16 and the kept products.
+* ``oracle.mlp`` -- float64 forward, chain-rule gradient and Adam step of the
+  cost model used for learned tree selection.
 
 Only the test-suite, the package smoke check and the benchmark's CPU-baseline
 leg may import this package.  The product path never calls it and shares no

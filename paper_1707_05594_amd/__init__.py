@@ -21,7 +21,10 @@ TK_OK, TK_EINVAL, TK_ENOMEM, TK_EDEVICE, TK_ENUMERIC, TK_EUNSUPPORTED = 0, -1, -
 TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 TK_C_FP64, TK_C_FP32, TK_C_BF16, TK_C_BF16X3 = 0, 1, 2, 3
 TREE_KINDS = {"dp": 0, "chain": 1, "chain_k": 2, "chain_h": 3, "balanced": 4}
+TK_TILE_AUTO, TK_TILE_STAGED, TK_TILE_SPLITK, TK_TILE_COUNT = 0, 1, 2, 3
+TK_FEATURES = 12
 COMPUTE = {"fp64": TK_C_FP64, "fp32": TK_C_FP32, "bf16": TK_C_BF16, "bf16x3": TK_C_BF16X3}
+DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 MAX_MODES = 12
 
 
@@ -46,6 +49,7 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
+_fp = ctypes.POINTER(ctypes.c_float)
 
 _SIGS = {
     "ttm_tree_plan": ([ctypes.c_int, _i64p, _i64p, ctypes.c_int, ctypes.c_int,
@@ -78,6 +82,24 @@ _SIGS = {
     "tk_gram": ([ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp], ctypes.c_int),
     "tk_eig_leading": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
                        ctypes.c_int),
+    "tk_ttm_features": ([_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _fp],
+                        ctypes.c_int),
+    "tk_time_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp,
+                     ctypes.c_int, ctypes.c_int, _vp, _fp], ctypes.c_int),
+    "tk_plan_set_tiles": ([_vp, ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
+    "tk_plan_get_tiles": ([_vp, ctypes.c_int, _ip, ctypes.c_int, _ip], ctypes.c_int),
+    "tk_mlp_param_count": ([ctypes.c_int, ctypes.c_int], ctypes.c_int64),
+    "tk_mlp_create": ([ctypes.c_int, ctypes.c_int, _fp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tk_mlp_set_norm": ([_vp, _fp, _fp], ctypes.c_int),
+    "tk_mlp_get_params": ([_vp, _fp], ctypes.c_int),
+    "tk_mlp_set_params": ([_vp, _fp], ctypes.c_int),
+    "tk_mlp_forward": ([_vp, _fp, ctypes.c_int, _fp], ctypes.c_int),
+    "tk_mlp_loss_grad": ([_vp, _fp, _fp, ctypes.c_int, _fp, _fp], ctypes.c_int),
+    "tk_mlp_train": ([_vp, _fp, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp],
+                     ctypes.c_int),
+    "tk_mlp_free": ([_vp], None),
+    "tk_plan_learned": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip, _dp],
+                        ctypes.c_int),
     "tk_last_error": ([], ctypes.c_char_p),
 }
 
@@ -166,6 +188,28 @@ class Plan:
 
     def select(self, rank):
         _check(lib().tk_plan_select(self._h, rank))
+
+    def set_tiles(self, rank, tiles):
+        arr = (ctypes.c_int * len(tiles))(*[int(t) for t in tiles])
+        _check(lib().tk_plan_set_tiles(self._h, rank, arr, len(tiles)))
+
+    def tiles(self, rank=0):
+        n = ctypes.c_int()
+        _check(lib().tk_plan_get_tiles(self._h, rank, None, 0, ctypes.byref(n)))
+        arr = (ctypes.c_int * n.value)()
+        _check(lib().tk_plan_get_tiles(self._h, rank, arr, n.value, ctypes.byref(n)))
+        return list(arr)
+
+    def learned(self, model, tdtype="f32", compute="fp32", margin=0.02):
+        """Select a held tree and per-node kernels by the cost model; returns
+        (chosen rank, predicted ms per rank)."""
+        import numpy as np
+        chosen = ctypes.c_int()
+        pred = np.zeros(self.count, dtype=np.float64)
+        _check(lib().tk_plan_learned(self._h, model.handle, DTYPES[tdtype], COMPUTE[compute],
+                                     float(margin), ctypes.byref(chosen),
+                                     pred.ctypes.data_as(_dp)))
+        return chosen.value, pred
 
 
 def ttm_tree_plan(L, K, kind="dp", topk=1) -> Plan:
@@ -342,3 +386,94 @@ def eig_leading(S, K, V0=None, F=None, evals=None, stream=None):
                                 _dev_ptr(V0) if V0 is not None else None, _dev_ptr(F),
                                 _dev_ptr(evals), _stream_ptr(stream)))
     return F, evals
+
+
+# ----------------------------------------------------------------------------- cost model --
+def _f32(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def ttm_features(A, L, B, K, in_dtype="f32", compute="fp32", tile=TK_TILE_AUTO):
+    """Cost-model features of one TTM node (TK_FEATURES floats)."""
+    import numpy as np
+    out = np.zeros(TK_FEATURES, dtype=np.float32)
+    _check(lib().tk_ttm_features(int(A), int(L), int(B), int(K), DTYPES[in_dtype],
+                                 COMPUTE[compute], int(tile), out.ctypes.data_as(_fp)))
+    return out
+
+
+def time_ttm(inp, A, L, B, F, K, out, compute="fp32", tile=TK_TILE_AUTO, reps=5, stream=None):
+    """Average time (ms) of the TTM node kernel on device tensors (HIP events)."""
+    ms = ctypes.c_float()
+    _check(lib().tk_time_ttm(_dtype_code(inp), COMPUTE[compute], _dev_ptr(inp), int(A), int(L),
+                             int(B), _dev_ptr(F), int(K), _dev_ptr(out), int(tile), int(reps),
+                             _stream_ptr(stream), ctypes.byref(ms)))
+    return float(ms.value)
+
+
+def mlp_param_count(in_dim, hidden):
+    return int(lib().tk_mlp_param_count(int(in_dim), int(hidden)))
+
+
+class MLP:
+    """The cost model's MLP on the device (forward, backward, Adam in libtucker)."""
+
+    def __init__(self, in_dim, hidden, params):
+        p = _f32(params).reshape(-1)
+        if p.size != mlp_param_count(in_dim, hidden):
+            raise ValueError("wrong number of parameters")
+        self.in_dim, self.hidden = int(in_dim), int(hidden)
+        h = _vp()
+        _check(lib().tk_mlp_create(self.in_dim, self.hidden, p.ctypes.data_as(_fp),
+                                   ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.tk_mlp_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_norm(self, mu, sigma):
+        mu, sigma = _f32(mu), _f32(sigma)
+        _check(lib().tk_mlp_set_norm(self._h, mu.ctypes.data_as(_fp), sigma.ctypes.data_as(_fp)))
+
+    def params(self):
+        import numpy as np
+        out = np.zeros(mlp_param_count(self.in_dim, self.hidden), dtype=np.float32)
+        _check(lib().tk_mlp_get_params(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def set_params(self, params):
+        p = _f32(params).reshape(-1)
+        _check(lib().tk_mlp_set_params(self._h, p.ctypes.data_as(_fp)))
+
+    def forward(self, X):
+        import numpy as np
+        X = _f32(X)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        _check(lib().tk_mlp_forward(self._h, X.ctypes.data_as(_fp), X.shape[0],
+                                    out.ctypes.data_as(_fp)))
+        return out
+
+    def loss_grad(self, X, y):
+        import numpy as np
+        X, y = _f32(X), _f32(y)
+        loss = ctypes.c_float()
+        g = np.zeros(mlp_param_count(self.in_dim, self.hidden), dtype=np.float32)
+        _check(lib().tk_mlp_loss_grad(self._h, X.ctypes.data_as(_fp), y.ctypes.data_as(_fp),
+                                      X.shape[0], ctypes.byref(loss), g.ctypes.data_as(_fp)))
+        return float(loss.value), g
+
+    def train(self, X, y, steps, lr):
+        import numpy as np
+        X, y = _f32(X), _f32(y)
+        losses = np.zeros(int(steps), dtype=np.float32)
+        _check(lib().tk_mlp_train(self._h, X.ctypes.data_as(_fp), y.ctypes.data_as(_fp),
+                                  X.shape[0], int(steps), float(lr), losses.ctypes.data_as(_fp)))
+        return losses
+

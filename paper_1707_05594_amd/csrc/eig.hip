@@ -38,7 +38,7 @@
 
 namespace tk {
 
-constexpr int kEigPMax = 48;
+constexpr int kEigPMax = 64;
 constexpr int kEigThreads = 256;
 constexpr int kEigLdsMax = 160 * 1024;
 
@@ -165,20 +165,31 @@ __device__ __forceinline__ void cholqr_pass(EigMem<PS>& m, int L) {
   }
   if (tid == 0) sh.minpiv = minpiv;
   __syncthreads();
-  // V <- V D R^{-1}; row i solves x R = v D (R = transpose of the lower factor in H)
+  // V <- V M with M = D R^{-1} (R = transpose of the lower factor Lc in H): row
+  // i of the result solves x R = v D.  Column c of M follows from the earlier
+  // ones, M(:,c) = (d_c e_c - sum_{k<c} M(:,k) Lc[c][k]) / Lc[c][c]; thread j
+  // builds row j of M in H2 (a dead column has a zero reciprocal: zero column).
+  double* M = m.H2;
+  if (tid < PS) {
+    const int j = tid;
+    for (int c = 0; c < PS; ++c) {
+      double acc = (j == c) ? sh.dscale[c] : 0.0;
+      for (int k = j; k < c; ++k) acc -= M[j * PS + k] * H[c * PS + k];
+      M[j * PS + c] = acc * sh.cs_c[c];
+    }
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < L; i += kEigThreads) {
     double x[PS];
 #pragma unroll
-    for (int j = 0; j < PS; ++j) x[j] = V[i * PS + j] * sh.dscale[j];
+    for (int j = 0; j < PS; ++j) x[j] = V[i * PS + j];
+#pragma unroll 2
+    for (int c = 0; c < PS; ++c) {
+      double sx = 0.0;
 #pragma unroll
-    for (int j = 0; j < PS; ++j) {
-      double s = x[j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) s -= x[k] * H[j * PS + k];
-      x[j] = s * sh.cs_c[j];
+      for (int j = 0; j < PS; ++j) sx = fma(x[j], M[j * PS + c], sx);
+      V[i * PS + c] = sx;
     }
-#pragma unroll
-    for (int j = 0; j < PS; ++j) V[i * PS + j] = x[j];
   }
   __syncthreads();
 }
@@ -361,26 +372,31 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     }
     double* V = m.V;
     double* W = m.W;
-    // ---- W = S V (S symmetric: threads walk rows i, reading S[l][i] coalesced)
+    // ---- W = S V (S symmetric: threads walk rows i, reading S[l][i] coalesced),
+    // in column chunks of kCW so the accumulators stay in registers
+    constexpr int kCW = PS % 16 == 0 ? 16 : 8;  // divides PS (a multiple of 8)
+    static_assert(PS % kCW == 0, "column chunks must tile the padded width");
     for (int i = tid; i < L; i += kEigThreads) {
-      double acc[PS];
+      for (int c0 = 0; c0 < PS; c0 += kCW) {
+        double acc[kCW];
 #pragma unroll
-      for (int j = 0; j < PS; ++j) acc[j] = 0.0;
-      constexpr int kPre = 8;
-      for (int l0 = 0; l0 < L; l0 += kPre) {
-        double sv[kPre];
+        for (int j = 0; j < kCW; ++j) acc[j] = 0.0;
+        constexpr int kPre = 8;
+        for (int l0 = 0; l0 < L; l0 += kPre) {
+          double sv[kPre];
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) sv[u] = (l0 + u < L) ? S[(int64_t)(l0 + u) * L + i] : 0.0;
+          for (int u = 0; u < kPre; ++u) sv[u] = (l0 + u < L) ? S[(int64_t)(l0 + u) * L + i] : 0.0;
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-          const int l = min(l0 + u, L - 1);  // sv is 0 past the end
-          const double* vr = V + l * PS;
+          for (int u = 0; u < kPre; ++u) {
+            const int l = min(l0 + u, L - 1);  // sv is 0 past the end
+            const double* vr = V + l * PS + c0;
 #pragma unroll
-          for (int j = 0; j < PS; ++j) acc[j] = fma(sv[u], vr[j], acc[j]);
+            for (int j = 0; j < kCW; ++j) acc[j] = fma(sv[u], vr[j], acc[j]);
+          }
         }
-      }
 #pragma unroll
-      for (int j = 0; j < PS; ++j) W[i * PS + j] = acc[j];
+        for (int j = 0; j < kCW; ++j) W[i * PS + c0 + j] = acc[j];
+      }
     }
     __syncthreads();
     // ---- H = V^T W (symmetrised)
@@ -402,42 +418,39 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
       sh.perm[rank] = j;
     }
     __syncthreads();
-    // ---- Ritz vectors: V <- V Z(:, perm), W <- W Z(:, perm)
-    for (int i = tid; i < L; i += kEigThreads) {
-      double xv[PS], xw[PS];
+    // ---- Ritz vectors: V <- V Z(:, perm), W <- W Z(:, perm), one block at a time
+    for (int pass = 0; pass < 2; ++pass) {
+      double* X = pass == 0 ? V : W;
+      for (int i = tid; i < L; i += kEigThreads) {
+        double x[PS];
 #pragma unroll
-      for (int j = 0; j < PS; ++j) {
-        xv[j] = V[i * PS + j];
-        xw[j] = W[i * PS + j];
-      }
-#pragma unroll 4
-      for (int c = 0; c < PS; ++c) {
-        const int src = sh.perm[c];
-        double sv = 0.0, sw = 0.0;
+        for (int j = 0; j < PS; ++j) x[j] = X[i * PS + j];
+#pragma unroll 2
+        for (int c = 0; c < PS; ++c) {
+          const int src = sh.perm[c];
+          double sx = 0.0;
 #pragma unroll
-        for (int j = 0; j < PS; ++j) {
-          const double z = m.Z[j * PS + src];
-          sv = fma(xv[j], z, sv);
-          sw = fma(xw[j], z, sw);
+          for (int j = 0; j < PS; ++j) sx = fma(x[j], m.Z[j * PS + src], sx);
+          X[i * PS + c] = sx;
         }
-        V[i * PS + c] = sv;
-        W[i * PS + c] = sw;
       }
     }
     __syncthreads();
-    // ---- residuals of the leading K Ritz pairs
+    // ---- residuals of the leading K Ritz pairs (column chunks of kCW)
     {
-      double part[PS];
+      for (int c0 = 0; c0 < PS; c0 += kCW) {
+        double part[kCW];
 #pragma unroll
-      for (int j = 0; j < PS; ++j) part[j] = 0.0;
-      for (int i = tid; i < L; i += kEigThreads) {
+        for (int j = 0; j < kCW; ++j) part[j] = 0.0;
+        for (int i = tid; i < L; i += kEigThreads) {
 #pragma unroll
-        for (int j = 0; j < PS; ++j) {
-          const double r = W[i * PS + j] - sh.theta[sh.perm[j]] * V[i * PS + j];
-          part[j] = fma(r, r, part[j]);
+          for (int j = 0; j < kCW; ++j) {
+            const double r = W[i * PS + c0 + j] - sh.theta[sh.perm[c0 + j]] * V[i * PS + c0 + j];
+            part[j] = fma(r, r, part[j]);
+          }
         }
+        block_sum_vec<kCW>(part, sh.red, sh.dscale + c0);
       }
-      block_sum_vec<PS>(part, sh.red, sh.dscale);
       if (tid == 0) {
         const double t0 = fabs(sh.theta[sh.perm[0]]);
         double worst = 0.0;
@@ -513,10 +526,15 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
   if (tid == 0 && iters_out) iters_out[mi] = used + 1;
 }
 
+// Up to L = 64 the block is the whole space (p = L), so every solve is a full
+// Jacobi eigen-decomposition: exact in one step whatever the eigenvalue gaps,
+// which matters when the trailing K_n eigenvalues sit in an almost flat noise
+// spectrum (a planted core of lower numerical rank than K_n).  Larger L uses
+// subspace iteration with a block of K + 16 columns (at most 48).
 int eig_block_size(int L, int K, int64_t rank_bound) {
   if (L <= kEigPMax) return L;
   int64_t p = K + 16;
-  p = std::min<int64_t>(p, kEigPMax);
+  p = std::min<int64_t>(p, 48);
   p = std::min<int64_t>(p, L);
   p = std::min<int64_t>(p, std::max<int64_t>(rank_bound, K));
   return (int)std::max<int64_t>(p, K);
@@ -556,6 +574,8 @@ hipError_t init_lds_limit() {
     if (a == hipSuccess) a = set_attr<32>(lim);
     if (a == hipSuccess) a = set_attr<40>(lim);
     if (a == hipSuccess) a = set_attr<48>(lim);
+    if (a == hipSuccess) a = set_attr<56>(lim);
+    if (a == hipSuccess) a = set_attr<64>(lim);
     if (a != hipSuccess) {
       (void)hipGetLastError();
       lim = 64 * 1024 - (int)sizeof(EigSmall);
@@ -605,6 +625,8 @@ hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int
     TK_EIG_CASE(32)
     TK_EIG_CASE(40)
     TK_EIG_CASE(48)
+    TK_EIG_CASE(56)
+    TK_EIG_CASE(64)
     default:
       return hipErrorInvalidValue;
   }
@@ -612,6 +634,6 @@ hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int
   return hipGetLastError();
 }
 
-int eig_max_K() { return kEigPMax; }
+int eig_max_K() { return 48; }
 
 }  // namespace tk

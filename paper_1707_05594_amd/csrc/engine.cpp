@@ -33,13 +33,6 @@ using namespace tk;
 
 namespace {
 
-#define TK_HIP(call)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(TK_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
-  } while (0)
-
 int dalloc(void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
@@ -57,18 +50,6 @@ size_t dtype_size(int dt) { return dt == TK_F64 ? 8 : (dt == TK_F32 ? 4 : 2); }
 int64_t align64(int64_t x) { return (x + 63) & ~(int64_t)63; }
 
 // [A, L, B] view of a tensor whose modes in `pre` are already multiplied, along mode n.
-void view(const Shape& s, uint32_t pre, int n, int64_t* A, int64_t* L, int64_t* B) {
-  int64_t a = 1, b = 1;
-  for (int j = 0; j < s.N; ++j) {
-    const int64_t d = ((pre >> j) & 1u) ? s.K[j] : s.L[j];
-    if (j < n) a *= d;
-    if (j > n) b *= d;
-  }
-  *A = a;
-  *L = ((pre >> n) & 1u) ? s.K[n] : s.L[n];
-  *B = b;
-}
-
 }  // namespace
 
 struct tk_ctx {
@@ -82,6 +63,7 @@ struct tk_ctx {
   // modes form the core at FP32.
   int core_compute = TK_C_FP32;
   std::vector<int> node_compute;  // per tree node: compute, or core_compute on the fold path
+  std::vector<int> node_tile;     // per tree node: TK_TILE_* kernel choice from the plan
   int wdtype = TK_F32;  // element type of intermediates and compute-precision factors
   const void* T = nullptr;
   hipStream_t st = nullptr;
@@ -323,7 +305,7 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
     if (!nd.is_leaf) {
       // children of the root stream T (too large to stay in cache between them)
       TK_HIP(launch_ttm(in_dt, c->node_compute[u], in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
-                        c->wsp(c->node_off[u]), c->st, nd.parent < 0));
+                        c->wsp(c->node_off[u]), c->st, nd.parent < 0, c->node_tile[u]));
     } else {
       const int n = nd.mode;
       TK_HIP(launch_gram(in_dt, in, A, L, B, c->S + c->sofs[n], c->gpart, c->st));
@@ -433,7 +415,9 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
 
   // ---- plan
   if (plan) {
-    c->tree = plan->trees[std::min<int>(plan->selected, (int)plan->trees.size() - 1)];
+    const int r = std::min<int>(plan->selected, (int)plan->trees.size() - 1);
+    c->tree = plan->trees[r];
+    if (r < (int)plan->tiles.size() && !plan->tiles[r].empty()) c->node_tile = plan->tiles[r];
   } else {
     tk_plan* p = nullptr;
     if (int rc = ttm_tree_plan(N, L, K, TK_TREE_DP, 1, &p)) return bail(rc);
@@ -441,6 +425,7 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     tk_plan_free(p);
   }
   const auto& nodes = c->tree.nodes;
+  c->node_tile.resize(nodes.size(), TK_TILE_AUTO);
   c->node_off.assign(nodes.size(), 0);
   int64_t ws = 0;
   int64_t best_leaf = -1;

@@ -36,6 +36,20 @@ struct Shape {
   }
 };
 
+// [A, L, B] view of a node's input: In(u) has multiplied the modes in `pre`
+// (lengths K there, L elsewhere); the node multiplies along mode n.
+inline void view(const Shape& s, uint32_t pre, int n, int64_t* A, int64_t* L, int64_t* B) {
+  int64_t a = 1, b = 1;
+  for (int j = 0; j < s.N; ++j) {
+    const int64_t d = ((pre >> j) & 1u) ? s.K[j] : s.L[j];
+    if (j < n) a *= d;
+    if (j > n) b *= d;
+  }
+  *A = a;
+  *L = ((pre >> n) & 1u) ? s.K[n] : s.L[n];
+  *B = b;
+}
+
 // Checks 2 <= N <= TK_MAX_MODES, 1 <= K_n <= L_n, K_n <= prod_{m!=n} K_m,
 // prod(L) < 2^62.  Fills `s`.  Returns TK_OK or TK_EINVAL (with message).
 int make_shape(int N, const int64_t* L, const int64_t* K, Shape* s);
@@ -56,5 +70,15 @@ struct tk_plan {
   int kind = 0;
   int selected = 0;  // rank used by hooi_init
   std::vector<tk::Tree> trees;
+  // per tree: TK_TILE_* of every node (empty: TK_TILE_AUTO everywhere)
+  std::vector<std::vector<int>> tiles;
   uint64_t entries = 0, lookups = 0;
 };
+
+// Return TK_EDEVICE with the HIP error text from a function returning int.
+#define TK_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return tk::fail(TK_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)

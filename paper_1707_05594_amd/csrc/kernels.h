@@ -9,9 +9,10 @@ namespace tk {
 
 // TTM node: Out[a,k,b] = sum_l F[l,k] In[a,l,b]  (ttm.hip)
 // stream_in: the input is read once (streamed past the caches)
+// tile: TK_TILE_* kernel choice (FP64 compute ignores it)
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
                       const void* F, int64_t K, void* out, hipStream_t st,
-                      bool stream_in = false);
+                      bool stream_in = false, int tile = 0);
 int ttm_max_L();
 
 // Gram S = Y_(n) Y_(n)^T (gram.hip); `part` holds gram_workspace_elems(L, A*B) doubles

@@ -646,13 +646,23 @@ hipError_t launch_f32_nt(Path path, int kg, const TIn* in, int64_t A, int L, int
   }
 }
 
+// Tile override: TK_TILE_SPLITK halves the K-group instance (twice the
+// K-chunks, so more blocks that re-read the input from cache).
+int split_kg(int kg) {
+  int pick = 1;
+  for (int c : kInst)
+    if (c <= std::max(1, kg / 2)) pick = c;
+  return pick;
+}
+
 template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
-                      float* out, bool stream_in, hipStream_t st) {
+                      float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
-  const Path path = choose_path(in, out, L, B);
-  const int kg = pick_kg(K, std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L)),
-                         grid_blocks(path, A, B));
+  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
+  int kg = pick_kg(K, std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L)),
+                   grid_blocks(path, A, B));
+  if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in)
     return launch_f32_nt<TIn, true>(path, kg, in, A, L, B, F, K, out, st);
   return launch_f32_nt<TIn, false>(path, kg, in, A, L, B, F, K, out, st);
@@ -705,13 +715,14 @@ hipError_t launch_bf16_nt(Path path, int kg, const TIn* in, int64_t A, int L, in
 // at least as accurate as the mode asks for.
 template <typename TIn>
 hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
-                       float* out, bool stream_in, bool x3, hipStream_t st) {
-  const Path path = choose_path(in, out, L, B);
-  if (path == Path::kTile) return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, st);
+                       float* out, bool stream_in, bool x3, int tile, hipStream_t st) {
+  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
+  if (path == Path::kTile) return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, tile, st);
   const int per_group = 32 * ((L + 3) / 4) * (x3 ? 2 : 1);  // LDS bytes per K-group
   int kg_cap = std::max(1, kLdsBudget / per_group);
   if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
-  const int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
+  int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
+  if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in) {
     if (x3) return launch_bf16_nt<TIn, true, true>(path, kg, in, A, L, B, F, K, out, st);
     return launch_bf16_nt<TIn, true, false>(path, kg, in, A, L, B, F, K, out, st);
@@ -741,7 +752,8 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }
 
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
-                      const void* F, int64_t K, void* out, hipStream_t st, bool stream_in) {
+                      const void* F, int64_t K, void* out, hipStream_t st, bool stream_in,
+                      int tile) {
   if (A * B == 0 || K == 0) return hipSuccess;
   if (compute == TK_C_FP64) {
     const int Li = (int)L;
@@ -759,15 +771,15 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
     const bool x3 = compute == TK_C_BF16X3;
     if (in_dtype == TK_F32)
       return launch_bf16<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
-                                (float*)out, stream_in, x3, st);
+                                (float*)out, stream_in, x3, tile, st);
     return launch_bf16<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
-                                 (float*)out, stream_in, x3, st);
+                                 (float*)out, stream_in, x3, tile, st);
   }
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
-                             (float*)out, stream_in, st);
+                             (float*)out, stream_in, tile, st);
   return launch_f32<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
-                              (float*)out, stream_in, st);
+                              (float*)out, stream_in, tile, st);
 }
 
 }  // namespace tk

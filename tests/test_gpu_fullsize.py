@@ -1,0 +1,136 @@
+"""Full-size parity on the GPU: the 200^4 rank-20 FP32 tensor in the launch
+configuration the benchmark times (DP tree, FP32 compute), and the 80^5
+rank-10 BF16-stored tensor in the reduced-precision modes.
+
+The oracle cannot form a whole leaf at this size, so sampled leaf entries are
+computed one by one from their definition (a slice of T contracted with one
+column of each other factor); everything else is checked through properties
+that hold at any size: the Gram invariant trace(F_n^T S_n F_n) = ||G||^2 for
+every n, symmetric Grams, orthonormal factors that are eigenvectors of their
+Gram, and the identity error against the FP64 explicit residual."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hooi as O
+from tests.gpu_util import rel_err, torch_dev
+
+pytestmark = pytest.mark.gpu
+tk = pytest.importorskip("paper_1707_05594_amd")
+
+SAMPLES = 48
+
+
+def _sample_indices(L, K, n, count, seed):
+    g = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        out.append(tuple(int(g.integers(0, L[j])) if j == n else int(g.integers(0, K[j]))
+                         for j in range(len(L))))
+    return out
+
+
+def _leaf_at(leaf, idx):
+    return float(leaf[idx])
+
+
+@pytest.fixture(scope="module")
+def c2():
+    torch, dev = torch_dev()
+    print("generating planted 200^4 rank-20 FP32", flush=True)
+    T, info = synth.workload("planted_200x200x200x200_r20_f32")
+    Td = torch.from_numpy(T).to(dev)
+    torch.cuda.synchronize()
+    return T, info, Td
+
+
+def test_c2_sampled_leaves_and_gram_invariant(c2):
+    T, info, Td = c2
+    L, K = info["L"], info["K"]
+    print("200^4: HOSVD start, one tree pass", flush=True)
+    ctx = tk.hooi_init(Td, K, compute="fp32", plan=tk.ttm_tree_plan(L, K))
+    # FP32-representable factors, so both sides multiply by the same values
+    F = [f.astype(np.float32).astype(np.float64) for f in ctx.factors()]
+    ctx.set_factors(F)
+    ctx.tree_pass()
+    traces = []
+    for n in range(4):
+        leaf = ctx.leaf(n)
+        assert leaf.shape == tuple(K[j] if j != n else L[j] for j in range(4))
+        idx = _sample_indices(L, K, n, SAMPLES, 100 + n)
+        got = np.array([_leaf_at(leaf, i) for i in idx])
+        want = O.leaf_entries(T, F, n, idx)
+        print(f"mode {n}: sampled leaf rel err {rel_err(got, want):.3e}", flush=True)
+        assert rel_err(got, want) < 1e-5
+        S = ctx.gram(n)
+        assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+        # the Gram of the GPU leaf, formed here in FP64 from the leaf itself
+        Y = np.moveaxis(leaf, n, 0).reshape(L[n], -1)
+        assert rel_err(S, Y @ Y.T) < 1e-12
+        traces.append(float(np.trace(F[n].T @ S @ F[n])))
+    traces = np.array(traces)
+    # ||T x_1 F_1^T ... x_N F_N^T||^2 from every leaf (FP32 leaves: 1e-5)
+    assert np.ptp(traces) < 1e-5 * traces.max()
+
+
+def test_c2_iterations_properties(c2):
+    T, info, Td = c2
+    L, K = info["L"], info["K"]
+    print("200^4: HOSVD + 3 HOOI invocations", flush=True)
+    ctx = tk.hooi_init(Td, K, compute="fp32")
+    errs = ctx.iterate(3)
+    e_exp = ctx.error_explicit()
+    print(f"errors {errs}, explicit {e_exp:.9e}", flush=True)
+    # planted rank-20 tensor with 1e-3 relative noise: the error sits at the noise
+    # level (the noise outside the planted subspaces: (1 - 20^4/200^4)^(1/2))
+    assert all(abs(e - 1e-3) < 2e-5 for e in errs)
+    # identity error vs FP64 residual: FP32 ||G||^2 perturbs e^2 by ~1e-9 absolute
+    assert abs(errs[-1] - e_exp) < 2e-3 * e_exp
+    for n in range(4):
+        Fn = ctx.factor(n)
+        assert np.abs(Fn.T @ Fn - np.eye(K[n])).max() < 1e-12
+        # eigenvectors of the Gram of the last tree pass
+        S = ctx.gram(n)
+        lam = np.diag(Fn.T @ S @ Fn)
+        assert np.all(np.diff(lam) <= 1e-9 * lam[0])  # descending
+        assert np.linalg.norm(S @ Fn - Fn * lam) < 1e-9 * np.linalg.norm(S)
+        # sign rule: the largest-magnitude entry of each column is positive
+        cols = np.arange(K[n])
+        assert np.all(Fn[np.abs(Fn).argmax(axis=0), cols] > 0)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    torch, dev = torch_dev()
+    print("generating planted 80^5 rank-10 BF16", flush=True)
+    T, info = synth.workload("planted_80x80x80x80x80_r10_bf16")
+    Td = torch.from_numpy(T.view(np.int16)).view(torch.bfloat16).to(dev)
+    T32 = (T.astype(np.uint32) << np.uint32(16)).view(np.float32)  # exact upcast
+    torch.cuda.synchronize()
+    del T
+    return T32, info, Td
+
+
+@pytest.mark.parametrize("compute,bound", [("bf16x3", 1e-4), ("bf16", 1.5e-2)])
+def test_c3_bf16_storage_sampled_leaves(c3, compute, bound):
+    T32, info, Td = c3
+    L, K = info["L"], info["K"]
+    print(f"80^5 BF16 storage, {compute}: one tree pass", flush=True)
+    ctx = tk.hooi_init(Td, K, compute=compute)
+    F = [f.astype(np.float32).astype(np.float64) for f in ctx.factors()]
+    ctx.set_factors(F)
+    ctx.tree_pass()
+    for n in range(5):
+        leaf = ctx.leaf(n)
+        idx = _sample_indices(L, K, n, SAMPLES // 2, 200 + n)
+        got = np.array([_leaf_at(leaf, i) for i in idx])
+        want = O.leaf_entries(T32, F, n, idx)
+        err = rel_err(got, want)
+        print(f"mode {n}: sampled leaf rel err {err:.3e} (bound {bound})", flush=True)
+        assert err < bound
+    errs = ctx.iterate(2)
+    e_exp = ctx.error_explicit()
+    print(f"errors {errs}, explicit {e_exp:.9e}", flush=True)
+    # core and error are formed at FP32 in these modes: identity vs residual
+    assert abs(errs[-1] - e_exp) < 1e-3 * e_exp
+    assert abs(e_exp - 1e-2) < 5e-4
