@@ -489,10 +489,15 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     j.V0_off = (int64_t)c->fofs[n];
     j.F_off = (int64_t)c->fofs[n];
     j.ev_off = (int64_t)c->kofs[n];
-    j.work_off = (int64_t)work;
-    work += eig_work_elems(j.L, j.p);
     c->Lmax = std::max(c->Lmax, j.L);
     c->pmax = std::max(c->pmax, j.p);
+  }
+  // A launch over all modes uses the block width of the widest job for every
+  // job, so each work area holds two L_n x padded(pmax) blocks.
+  for (int n = 0; n < N; ++n) {
+    EigJob& j = c->jobs_h[n];
+    j.work_off = (int64_t)work;
+    work += eig_work_elems(j.L, c->pmax);
   }
   // cold starts (HOSVD) use the full block; warm starts (previous factors)
   // need only K columns plus a little room to grow, which keeps the blocks in LDS

@@ -28,6 +28,8 @@ struct EigJob {
   int64_t S_off, V0_off, F_off, ev_off, work_off;
 };
 // Jobs [job0, job0 + count) of the device table; Lmax / pmax bound their L and p.
+// Every job of the launch uses the block width padded(pmax): its work area
+// must hold eig_work_elems(L_job, pmax) doubles (not its own p's).
 // status[job] is set on failure only (1: no convergence, 2: non-finite);
 // iters (nullable) receives the subspace steps each job used.
 hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int pmax,

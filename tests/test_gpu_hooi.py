@@ -142,6 +142,27 @@ def test_reduced_precision_iterations_match_oracle(compute):
     assert max(dists) < (1e-1 if compute == "bf16" else 1e-3)
 
 
+@pytest.mark.parametrize("L,K", [((64, 20, 12, 10), (6, 4, 3, 3)),
+                                 ((64, 48, 40, 32, 24, 16)[:4], (8, 8, 6, 6))])
+def test_modes_of_different_block_widths(L, K):
+    """Modes with different eigensolver block widths (p = L_n up to 64), so the
+    batched HOSVD launch runs every job at the widest width with V and W in
+    the global work area: HOSVD and three invocations against the oracle."""
+    T, _ = synth.planted(L, K, noise=1e-3, noise_kind="rel", dtype="f64", cfg=73)
+    print(f"block widths L={L} K={K}", flush=True)
+    ctx = tk.hooi_init(_device_T(T, "f64"), K, compute="fp64")
+    F0 = O.hosvd(T, K)
+    for n in range(len(L)):
+        assert subspace_dist(ctx.factor(n), F0[n]) < 1e-9
+    errs = ctx.iterate(3)
+    Fo, Go, errs_o = O.hooi(T, K, 3)
+    # identity error: ||G||^2 in FP64 moves e^2 by ~1e-16 ||T||^2-relative sums
+    for e, eo in zip(errs, errs_o):
+        assert abs(e * e - eo * eo) < 1e-13
+    for n in range(len(L)):
+        assert subspace_dist(ctx.factor(n), Fo[n]) < 1e-9
+
+
 def test_checkpoint_resume_is_exact_and_runs_are_deterministic():
     T, info = synth.workload("planted_64x64x64_r8_f64")
     K = info["K"]
