@@ -188,6 +188,46 @@ int tk_eig_iterations(tk_ctx* ctx, int* out);
 
 void hooi_free(tk_ctx* ctx);
 
+/* ---- batched HOOI over many independent tensors ---------------------------- */
+
+/* One HOOI invocation (Sec. 2.2, Jacobi form) for `count` tensors at a time,
+ * each with its own minimum-cost TTM-tree (Sec. 3.3).  Tree nodes of all
+ * tensors are grouped by depth; each depth is one launch of a persistent
+ * grouped TTM kernel draining a device queue of (node, tile) items; the
+ * leaves' Grams, the eigensolves, the folded cores and their norms are one
+ * launch each.  An iteration is captured in a HIP graph and replayed.
+ *   N[i]: modes of tensor i; L, K: the lengths concatenated over tensors
+ *   (sum of N[i] entries each), 1 <= K <= min(L, 16), L <= 512.
+ *   T_dev[i]: device pointer to tensor i (row-major, tdtype TK_F32 or
+ *   TK_BF16), borrowed.  compute: TK_C_FP32.  stream: caller's stream,
+ *   ordered before and after every call by events.
+ * Starts from HOSVD (FP64 eigensolver).  Errors TK_EINVAL, TK_EUNSUPPORTED,
+ * TK_ENOMEM, TK_EDEVICE, TK_ENUMERIC (eigensolver failure). */
+typedef struct tk_batch tk_batch;
+int hooi_batch_init(int count, const int* N, const int64_t* L, const int64_t* K, int tdtype,
+                    const void* const* T_dev, int compute, void* stream, tk_batch** out);
+/* rel_err: NULL or iters x count doubles; entry (t, i) is the error of tensor
+ * i's decomposition entering invocation t (t = 0: the HOSVD start).  After
+ * the call the factors are those of invocation iters - 1's output. */
+int hooi_batch_iterate(tk_batch* b, int iters, double* rel_err);
+/* Error of every tensor's current decomposition (count doubles). */
+int hooi_batch_error(tk_batch* b, double* rel_err);
+/* FP64 factor F_n of tensor i (L_n x K_n row-major), or all factors
+ * concatenated (tensor by tensor, mode by mode). */
+int hooi_batch_get_factor(tk_batch* b, int i, int n, double* host);
+int hooi_batch_get_factors(tk_batch* b, double* host);
+int hooi_batch_set_factors(tk_batch* b, const double* host);
+/* on = 0: enqueue every iteration eagerly instead of replaying the graph. */
+int hooi_batch_use_graph(tk_batch* b, int on);
+/* Autotuner: times the tree levels with 1, 2, 4 and 8 persistent blocks per
+ * CU, keeps the fastest (ms: NULL or 4 floats) and re-captures the graph. */
+int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms);
+/* Multiply-adds and algorithmic bytes (inputs read once, outputs written
+ * once) of all tree nodes, tree levels and TTM work items. */
+int hooi_batch_stats(const tk_batch* b, uint64_t* tree_macs, uint64_t* tree_bytes, int* levels,
+                     int* ttm_items);
+void hooi_batch_free(tk_batch* b);
+
 /* ---- learned tree and kernel selection ------------------------------------ */
 
 /* Features of one TTM node for the cost model (TK_FEATURES floats):

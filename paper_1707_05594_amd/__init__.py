@@ -100,6 +100,17 @@ _SIGS = {
     "tk_mlp_free": ([_vp], None),
     "tk_plan_learned": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip, _dp],
                         ctypes.c_int),
+    "hooi_batch_init": ([ctypes.c_int, _ip, _i64p, _i64p, ctypes.c_int, ctypes.POINTER(_vp),
+                         ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "hooi_batch_iterate": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
+    "hooi_batch_error": ([_vp, _dp], ctypes.c_int),
+    "hooi_batch_get_factor": ([_vp, ctypes.c_int, ctypes.c_int, _dp], ctypes.c_int),
+    "hooi_batch_get_factors": ([_vp, _dp], ctypes.c_int),
+    "hooi_batch_set_factors": ([_vp, _dp], ctypes.c_int),
+    "hooi_batch_use_graph": ([_vp, ctypes.c_int], ctypes.c_int),
+    "hooi_batch_tune": ([_vp, _ip, _fp], ctypes.c_int),
+    "hooi_batch_stats": ([_vp, _u64p, _u64p, _ip, _ip], ctypes.c_int),
+    "hooi_batch_free": ([_vp], None),
     "tk_last_error": ([], ctypes.c_char_p),
 }
 
@@ -476,4 +487,83 @@ class MLP:
         _check(lib().tk_mlp_train(self._h, X.ctypes.data_as(_fp), y.ctypes.data_as(_fp),
                                   X.shape[0], int(steps), float(lr), losses.ctypes.data_as(_fp)))
         return losses
+
+
+# ----------------------------------------------------------------------------- batched HOOI --
+class Batch:
+    """Batched HOOI over a list of device tensors (borrowed: keep them alive)."""
+
+    def __init__(self, tensors, ranks, stream=None):
+        import numpy as np
+        self.tensors = list(tensors)
+        self.L = [tuple(int(x) for x in t.shape) for t in self.tensors]
+        self.K = [tuple(int(x) for x in k) for k in ranks]
+        if len(self.K) != len(self.L):
+            raise ValueError("one rank tuple per tensor")
+        dts = {_dtype_code(t) for t in self.tensors}
+        if len(dts) != 1:
+            raise ValueError("all tensors must share one dtype")
+        Ns = (ctypes.c_int * len(self.L))(*[len(l) for l in self.L])
+        Ls = _arr64([x for l in self.L for x in l])
+        Ks = _arr64([x for k in self.K for x in k])
+        ptrs = (_vp * len(self.tensors))(*[_dev_ptr(t).value for t in self.tensors])
+        h = _vp()
+        _check(lib().hooi_batch_init(len(self.L), Ns, Ls, Ks, dts.pop(), ptrs, TK_C_FP32,
+                                     _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.count = len(self.L)
+        self._nf = sum(l * k for L_, K_ in zip(self.L, self.K) for l, k in zip(L_, K_))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hooi_batch_free(self._h)
+            self._h = None
+
+    def iterate(self, iters=1):
+        """errors[t][i]: error of tensor i's decomposition entering invocation t."""
+        import numpy as np
+        out = np.zeros((iters, self.count), dtype=np.float64)
+        _check(lib().hooi_batch_iterate(self._h, int(iters), out.ctypes.data_as(_dp)))
+        return out
+
+    def error(self):
+        import numpy as np
+        out = np.zeros(self.count, dtype=np.float64)
+        _check(lib().hooi_batch_error(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def factor(self, i, n):
+        import numpy as np
+        out = np.empty((self.L[i][n], self.K[i][n]), dtype=np.float64)
+        _check(lib().hooi_batch_get_factor(self._h, i, n, out.ctypes.data_as(_dp)))
+        return out
+
+    def factors(self):
+        import numpy as np
+        flat = np.empty(self._nf, dtype=np.float64)
+        _check(lib().hooi_batch_get_factors(self._h, flat.ctypes.data_as(_dp)))
+        return flat
+
+    def set_factors(self, flat):
+        import numpy as np
+        flat = np.ascontiguousarray(flat, dtype=np.float64)
+        _check(lib().hooi_batch_set_factors(self._h, flat.ctypes.data_as(_dp)))
+
+    def use_graph(self, on=True):
+        _check(lib().hooi_batch_use_graph(self._h, 1 if on else 0))
+
+    def tune(self):
+        import numpy as np
+        bpc = ctypes.c_int()
+        ms = np.zeros(4, dtype=np.float32)
+        _check(lib().hooi_batch_tune(self._h, ctypes.byref(bpc), ms.ctypes.data_as(_fp)))
+        return bpc.value, ms
+
+    def stats(self):
+        m, b = ctypes.c_uint64(), ctypes.c_uint64()
+        lv, it = ctypes.c_int(), ctypes.c_int()
+        _check(lib().hooi_batch_stats(self._h, ctypes.byref(m), ctypes.byref(b), ctypes.byref(lv),
+                                      ctypes.byref(it)))
+        return dict(tree_macs=int(m.value), tree_bytes=int(b.value), levels=lv.value,
+                    ttm_items=it.value)
 

@@ -79,15 +79,16 @@ __device__ __forceinline__ void gram_load_tile(double (*X)[kGT], const TIn* __re
   }
 }
 
+// Partial Gram of column chunk `chunk` for tile pair `pair` -> one 64 x 64
+// block of `part`.
 template <typename TIn>
-__global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, int L, int64_t B,
-                                                    int64_t C, int64_t cchunk, int T,
-                                                    int npairs, double* __restrict__ part) {
-  __shared__ double Xi[kGC][kGT];
-  __shared__ double Xj[kGC][kGT];
+__device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int L, int64_t B,
+                                                  int64_t C, int64_t cchunk, int T, int npairs,
+                                                  double* __restrict__ part, int chunk, int pair,
+                                                  double (*Xi)[kGT], double (*Xj)[kGT]) {
   int ti, tj;
-  pair_of(blockIdx.y, T, &ti, &tj);
-  const int64_t cbeg = (int64_t)blockIdx.x * cchunk;
+  pair_of(pair, T, &ti, &tj);
+  const int64_t cbeg = (int64_t)chunk * cchunk;
   const int64_t cend = min(C, cbeg + cchunk);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   double acc[4][4];
@@ -115,11 +116,32 @@ __global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, i
         for (int s = 0; s < 4; ++s) acc[r][s] = fma(ai[r], bj[s], acc[r][s]);
     }
   }
-  double* out = part + ((int64_t)blockIdx.x * npairs + blockIdx.y) * (kGT * kGT);
+  double* out = part + ((int64_t)chunk * npairs + pair) * (kGT * kGT);
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int s = 0; s < 4; ++s) out[(4 * ty + r) * kGT + 4 * tx + s] = acc[r][s];
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, int L, int64_t B,
+                                                    int64_t C, int64_t cchunk, int T,
+                                                    int npairs, double* __restrict__ part) {
+  __shared__ double Xi[kGC][kGT];
+  __shared__ double Xj[kGC][kGT];
+  gram_partial_body<TIn>(Y, L, B, C, cchunk, T, npairs, part, blockIdx.x, blockIdx.y, Xi, Xj);
+}
+
+// Grouped Gram (batched HOOI): block b computes item b = (matrix, chunk, pair).
+template <typename TIn>
+__global__ __launch_bounds__(256) void gram_grouped_partial(const GramDesc* __restrict__ mats,
+                                                            const int4* __restrict__ items) {
+  __shared__ double Xi[kGC][kGT];
+  __shared__ double Xj[kGC][kGT];
+  const int4 w = items[blockIdx.x];
+  const GramDesc d = mats[w.x];
+  gram_partial_body<TIn>((const TIn*)d.Y, d.L, d.B, d.C, d.cchunk, d.T, d.npairs, d.part, w.y,
+                         w.z, Xi, Xj);
 }
 
 __global__ void gram_reduce(const double* __restrict__ part, int L, int T, int npairs,
@@ -141,6 +163,38 @@ __global__ void gram_reduce(const double* __restrict__ part, int L, int T, int n
   S[e] = s;
 }
 
+// Element e of the concatenated L_m x L_m results of all matrices: matrix m
+// with elem_off[m] <= e < elem_off[m + 1] (binary search), then as gram_reduce.
+__global__ void gram_grouped_reduce(const GramDesc* __restrict__ mats,
+                                    const int64_t* __restrict__ elem_off, int n_mats) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= elem_off[n_mats]) return;
+  int lo = 0, hi = n_mats - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (elem_off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GramDesc d = mats[lo];
+  const int64_t r = e - elem_off[lo];
+  const int L = d.L;
+  const int i = (int)(r / L), j = (int)(r % L);
+  int ii = i, jj = j;
+  if (ii / kGT > jj / kGT) {
+    ii = j;
+    jj = i;
+  }
+  const int ti = ii / kGT, tj = jj / kGT;
+  const int p = ti * d.T - ti * (ti - 1) / 2 + (tj - ti);
+  const int li = ii - ti * kGT, lj = jj - tj * kGT;
+  double s = 0.0;
+  for (int ch = 0; ch < d.nchunks; ++ch)
+    s += d.part[((int64_t)ch * d.npairs + p) * (kGT * kGT) + li * kGT + lj];
+  d.S[r] = s;
+}
+
 namespace {
 struct GramGeom {
   int T, npairs;
@@ -159,6 +213,41 @@ GramGeom gram_geom(int64_t L, int64_t C) {
   return g;
 }
 }  // namespace
+
+void gram_geometry(int64_t L, int64_t C, int64_t target_blocks, GramDesc* d) {
+  GramGeom g = gram_geom(L, C);
+  if (target_blocks > 0) {
+    // batched: aim for `target_blocks` blocks per matrix instead of 4096
+    int64_t cc = (C + std::max<int64_t>(1, target_blocks / g.npairs) - 1) /
+                 std::max<int64_t>(1, target_blocks / g.npairs);
+    cc = std::max<int64_t>(cc, 128);
+    cc = (cc + kGC - 1) / kGC * kGC;
+    g.cchunk = cc;
+    g.nchunks = (C + cc - 1) / cc;
+  }
+  d->L = (int)L;
+  d->C = C;
+  d->T = g.T;
+  d->npairs = g.npairs;
+  d->cchunk = g.cchunk;
+  d->nchunks = (int)g.nchunks;
+}
+
+hipError_t launch_gram_grouped(int in_dtype, const GramDesc* mats, const int4* items,
+                               int n_items, const int64_t* elem_off, int n_mats,
+                               int64_t total_elems, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  if (in_dtype == TK_F32)
+    hipLaunchKernelGGL(gram_grouped_partial<float>, dim3(n_items), dim3(256), 0, st, mats, items);
+  else
+    hipLaunchKernelGGL(gram_grouped_partial<uint16_t>, dim3(n_items), dim3(256), 0, st, mats,
+                       items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gram_grouped_reduce, dim3((unsigned)((total_elems + 255) / 256)), dim3(256),
+                     0, st, mats, elem_off, n_mats);
+  return hipGetLastError();
+}
 
 size_t gram_workspace_elems(int64_t L, int64_t C) {
   GramGeom g = gram_geom(L, C);

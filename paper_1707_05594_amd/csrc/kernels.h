@@ -15,10 +15,45 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
                       bool stream_in = false, int tile = 0);
 int ttm_max_L();
 
+// Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.
+struct TtmNodeDesc {
+  const void* in;
+  float* out;
+  const float* F;  // L x K row-major
+  int64_t A, B, nbt;
+  int L, K, na, nb;
+};
+// Tile geometry of the LDS-staged TTM for a node viewed as [A, L, B].
+void ttm_tile_geometry(int64_t A, int64_t B, int* na, int* nb, int64_t* nbt, int64_t* tiles);
+// items: (node, tile) pairs, node an index into `nodes` (the whole table);
+// counter: zeroed device int (the queue head);
+// grid: persistent blocks.  Every node has K <= 16 and L <= Lmax; in_dtype
+// TK_F32 or TK_BF16 for all nodes of the launch.
+hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
+                              int n_items, int* counter, int Lmax, int grid, hipStream_t st);
+
 // Gram S = Y_(n) Y_(n)^T (gram.hip); `part` holds gram_workspace_elems(L, A*B) doubles
 hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
                        double* part, hipStream_t st);
 size_t gram_workspace_elems(int64_t L, int64_t C);
+
+// Grouped Gram (batched HOOI): one descriptor per matrix; Y viewed as
+// [C / B, L, B] (F32 or BF16), partial sums in `part` (nchunks * npairs
+// 64 x 64 blocks), result S (L x L).
+struct GramDesc {
+  const void* Y;
+  double* S;
+  double* part;
+  int64_t B, C, cchunk;
+  int L, T, npairs, nchunks;
+};
+// Fills L, C, T, npairs, cchunk, nchunks; target_blocks > 0 sets the number
+// of blocks per matrix the column chunks aim for.
+void gram_geometry(int64_t L, int64_t C, int64_t target_blocks, GramDesc* d);
+// items: (matrix, chunk, pair, 0); elem_off: n_mats + 1 prefix sums of L_m^2.
+hipError_t launch_gram_grouped(int in_dtype, const GramDesc* mats, const int4* items,
+                               int n_items, const int64_t* elem_off, int n_mats,
+                               int64_t total_elems, hipStream_t st);
 
 // Leading eigenpairs (eig.hip).  One job per matrix: S (L x L) at S_base + S_off,
 // optional warm start V0 (L x K) at V0_base + V0_off (V0_off < 0: cold start),
@@ -47,6 +82,10 @@ int sumsq_partials();
 hipError_t launch_convert(int from, int to, const void* a, void* b, int64_t n, hipStream_t st);
 hipError_t launch_fill(double* a, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_int(int* a, int64_t n, int v, hipStream_t st);
+hipError_t launch_copy_f64(const double* a, double* b, int64_t n, hipStream_t st);  // kernel copy
+// out[s] = sum of squares of x[off[s] .. off[s+1]) for s < count (one block each)
+hipError_t launch_sumsq_segments(const float* x, const int64_t* off, int count, double* out,
+                                 hipStream_t st);
 hipError_t launch_residual(int dtype, const void* Tt, const double* Zp, const double* F0, int L0,
                            int K0, int64_t R, double* part, double* out, hipStream_t st);
 

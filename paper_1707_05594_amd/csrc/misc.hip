@@ -92,6 +92,44 @@ hipError_t launch_convert(int from, int to, const void* a, void* b, int64_t n, h
   return hipGetLastError();
 }
 
+__global__ void copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+hipError_t launch_copy_f64(const double* a, double* b, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+// Block s: out[s] = sum of squares of x[off[s] .. off[s + 1]), FP64, fixed order.
+__global__ __launch_bounds__(256) void sumsq_segments(const float* __restrict__ x,
+                                                      const int64_t* __restrict__ off,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t b = off[blockIdx.x], e = off[blockIdx.x + 1];
+  double s = 0.0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    const double v = x[i];
+    s = fma(v, v, s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t launch_sumsq_segments(const float* x, const int64_t* off, int count, double* out,
+                                 hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(sumsq_segments, dim3(count), dim3(256), 0, st, x, off, out);
+  return hipGetLastError();
+}
+
 __global__ void fill_i32(int* __restrict__ a, int64_t n, int v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = v;

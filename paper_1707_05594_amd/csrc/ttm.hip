@@ -413,19 +413,18 @@ __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
 // contiguous elements), then each thread reads its column from LDS.
 constexpr int kTileLC = 32;
 
+// One tile of na x nb output columns (all K rows of the K-chunk at k0):
+// index `tile` = at * nbt + bt over a-tiles and b-tiles of the node.
 template <int KG, typename TIn>
-__global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
-                                                    const float* __restrict__ F,
-                                                    float* __restrict__ out, int64_t A, int L,
-                                                    int64_t B, int Kt, int na, int nb,
-                                                    int64_t nbt) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void tile_body(const TIn* __restrict__ in, const float* __restrict__ F,
+                                          float* __restrict__ out, int64_t A, int L, int64_t B,
+                                          int Kt, int na, int nb, int64_t nbt, int64_t tile,
+                                          int k0, float* smem) {
   float* FT = smem;
   float* X = smem + 4 * L * KG;  // [kTileLC][256]
-  const int k0 = blockIdx.y * 4 * KG;
   stage_factor<KG>(FT, F, L, Kt, k0);
-  const int64_t at = blockIdx.x / nbt;
-  const int64_t bt = blockIdx.x - at * nbt;
+  const int64_t at = tile / nbt;
+  const int64_t bt = tile - at * nbt;
   const int64_t a0 = at * na;
   const int64_t b0 = bt * nb;
   const int nav = (int)min((int64_t)na, A - a0);
@@ -482,6 +481,39 @@ __global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
       const int k = k0 + 4 * g + m;
       if (k < Kt) q[(int64_t)k * B] = acc[g][m];
     }
+}
+
+template <int KG, typename TIn>
+__global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t A, int L,
+                                                    int64_t B, int Kt, int na, int nb,
+                                                    int64_t nbt) {
+  extern __shared__ float smem[];
+  tile_body<KG, TIn>(in, F, out, A, L, B, Kt, na, nb, nbt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+}
+
+// Grouped TTM for batched HOOI: the (node, tile) items of many nodes, drained
+// from a device queue by a persistent grid.  Each block takes the next item
+// with one atomic increment; every block leaves once the queue is empty.
+// Nodes have K <= 16 (one K-chunk of four groups) and L <= Lmax.
+template <typename TIn>
+__global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict__ nodes,
+                                                   const int2* __restrict__ items, int n_items,
+                                                   int* __restrict__ counter) {
+  extern __shared__ float smem[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every thread has read s_item and finished the previous item
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const TtmNodeDesc d = nodes[w.x];
+    tile_body<4, TIn>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.B, d.K, d.na, d.nb, d.nbt, w.y, 0,
+                      smem);
+  }
 }
 
 // ------------------------------------------------------------------ FP64 path --
@@ -747,6 +779,27 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 }
 
 }  // namespace
+
+void ttm_tile_geometry(int64_t A, int64_t B, int* na, int* nb, int64_t* nbt, int64_t* tiles) {
+  *nb = (int)std::min<int64_t>(B, 256);
+  *na = 256 / *nb;
+  *nbt = (B + *nb - 1) / *nb;
+  *tiles = ((A + *na - 1) / *na) * *nbt;
+}
+
+hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
+                              int n_items, int* counter, int Lmax, int grid, hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  const size_t lds = (size_t)16 * Lmax * 4 + (size_t)4 * kTileLC * 256;
+  grid = std::max(1, std::min(grid, n_items));
+  if (in_dtype == TK_F32)
+    hipLaunchKernelGGL(ttm_grouped<float>, dim3(grid), dim3(256), lds, st, nodes, items, n_items,
+                       counter);
+  else
+    hipLaunchKernelGGL(ttm_grouped<uint16_t>, dim3(grid), dim3(256), lds, st, nodes, items,
+                       n_items, counter);
+  return hipGetLastError();
+}
 
 // Largest L the TTM kernels accept (factor slice of at least one K-group in LDS).
 int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }

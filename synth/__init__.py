@@ -210,5 +210,7 @@ def batch_shapes(count: int = 512, cfg: int = 5, seed_idx: int = 0,
         L = [int(v) for v in g.integers(lmin, lmax + 1, size=N)]
         K = [int(v) for v in g.integers(kmin, kmax + 1, size=N)]
         K = [min(k, l) for k, l in zip(K, L)]
+        for n in range(N):  # a rank above the product of the others is unattainable
+            K[n] = min(K[n], int(np.prod([K[m] for m in range(N) if m != n])))
         out.append((tuple(L), tuple(K)))
     return out
