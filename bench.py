@@ -16,6 +16,8 @@ Prints ONE JSON line.  Extra objects:
   cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
                   host for a bounded sample: one HOOI invocation of the same
                   tensor.
+  batch        -- batched HOOI over 512 planted 3- and 4-mode tensors (grouped
+                  persistent TTM levels in a replayed HIP graph).
   mixed        -- the same HOOI with T stored as BF16, TTMs in bf16x3 and in
                   BF16 (BF16 MFMA); each run's factors are scored against the
                   FP32 tensor (FP64 explicit residual) beside the FP32 run's.
@@ -116,6 +118,82 @@ def cpu_baseline(T32, K, F0):
                 seconds=round(dt, 2))
 
 
+def batch_leg(steps, warmup, seq_count=64):
+    """Batched HOOI over the uneven 512-tensor batch (3- or 4-mode, L in
+    [32, 128], K in [4, 16], 1e-3 relative noise, FP32): iterations/s of the
+    whole batch, the tree's algorithmic bytes per iteration and the rate they
+    imply, plus the first `seq_count` tensors run one context after another
+    against the same tensors as one batch."""
+    import numpy as np
+    import torch
+
+    import paper_1707_05594_amd as tk
+    import synth
+    dev = torch.device("cuda:0")
+    shapes = synth.batch_shapes(512, cfg=5, seed_idx=0)
+    t0 = time.perf_counter()
+    devs = []
+    elems = 0
+    for i, T in synth.batch_tensors(shapes, noise=1e-3, dtype="f32", cfg=5):
+        devs.append(torch.from_numpy(T).to(dev))
+        elems += T.size
+        del T
+    torch.cuda.synchronize()
+    log(f"batch: generated and uploaded {len(shapes)} tensors ({elems:.3e} elements) in "
+        f"{time.perf_counter() - t0:.1f}s")
+    ranks = [K for _, K in shapes]
+    b = tk.Batch(devs, ranks)
+    bpc, tune_ms = b.tune()
+    st = b.stats()
+    F0 = b.factors()
+    if warmup > 0:
+        b.iterate(warmup)
+    b.set_factors(F0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    errs = b.iterate(steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t1) / steps
+    cur = b.error()
+    # the same first seq_count tensors: one context each, one after another
+    sub = list(range(seq_count))
+    bs = tk.Batch([devs[i] for i in sub], [ranks[i] for i in sub])
+    bs.tune()
+    bs.iterate(1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    bs.iterate(steps)
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t2) / steps
+    ctxs = [tk.hooi_init(devs[i], ranks[i], compute="fp32") for i in sub]
+    for c in ctxs:
+        c.iterate(1)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for c in ctxs:
+        c.iterate(steps)
+    torch.cuda.synchronize()
+    dt_s = (time.perf_counter() - t3) / steps
+    res = {"workload": "512 planted tensors, 3- or 4-mode, L in [32,128], K in [4,16], 1e-3 rel "
+                       "noise, FP32, HOSVD start, DP tree each",
+           "elements": int(elems), "value": round(1.0 / dt, 3), "unit": "batch HOOI iters/s",
+           "ms_per_step": round(1e3 * dt, 4), "tree_macs": st["tree_macs"],
+           "tree_bytes": st["tree_bytes"], "levels": st["levels"], "ttm_items": st["ttm_items"],
+           "tree_GBps_at_step_time": round(st["tree_bytes"] / dt / 1e9, 1),
+           "frac_hbm_peak": round(st["tree_bytes"] / dt / 1e9 / HBM_PEAK_GBS, 4),
+           "tuned_blocks_per_cu": bpc, "tune_level_ms": [round(float(x), 4) for x in tune_ms],
+           "rel_err_median": float(np.median(cur)), "rel_err_max": float(np.max(cur)),
+           "first_%d" % seq_count: {"batched_ms_per_step": round(1e3 * dt_b, 4),
+                                    "one_context_each_ms_per_step": round(1e3 * dt_s, 4),
+                                    "speedup": round(dt_s / dt_b, 2)}}
+    log(f"batch: {res['value']} it/s ({res['ms_per_step']} ms), tree {st['tree_bytes']/1e9:.1f} GB "
+        f"-> {res['tree_GBps_at_step_time']} GB/s; first {seq_count}: batched {1e3*dt_b:.2f} ms vs "
+        f"one context each {1e3*dt_s:.2f} ms")
+    del b, bs, ctxs, devs
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +201,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
                          "(reference dispatches for HBM counter calibration)")
@@ -222,6 +301,9 @@ def main():
             del ctxb
         out["mixed"] = mixed
         del Tb
+
+    if not args.skip_batch:
+        out["batch"] = batch_leg(args.steps, args.warmup)
 
     if not args.skip_cpu_baseline:
         log("timing the FP64 oracle on one HOOI invocation ...")

@@ -23,10 +23,16 @@ from __future__ import annotations
 import concurrent.futures as _cf
 import math
 import os
+import threading
 
 import numpy as np
 
 SEED_ROOT = 17070559
+
+# BLAS and LAPACK calls (QR, tensordot, dot) are serialised: concurrent calls
+# into the threaded BLAS from several Python threads have produced wrong
+# results, and batch_tensors draws tensors on a thread pool.
+_BLAS = threading.RLock()
 
 # Workload table: each entry names one synthetic workload by its sizes.
 WORKLOADS = {
@@ -58,7 +64,9 @@ def generator(cfg: int, idx: int = 0, stream: int = 0) -> np.random.Generator:
 
 def orthonormal(g: np.random.Generator, L: int, K: int) -> np.ndarray:
     """Q factor of the reduced QR of an N(0,1) L x K matrix (float64)."""
-    q, _ = np.linalg.qr(g.standard_normal((L, K)))
+    a = g.standard_normal((L, K))
+    with _BLAS:
+        q, _ = np.linalg.qr(a)
     return q
 
 
@@ -80,7 +88,8 @@ def _assemble(G: np.ndarray, U, dtype) -> np.ndarray:
     N = X.ndim
     for n in range(N):
         # contract axis n of X with columns of U_n; tensordot puts the new axis last
-        X = np.tensordot(X, U[n].astype(dtype).T, axes=([n], [0]))
+        with _BLAS:
+            X = np.tensordot(X, U[n].astype(dtype).T, axes=([n], [0]))
         X = np.moveaxis(X, -1, n)
     return np.ascontiguousarray(X)
 
@@ -152,12 +161,13 @@ def planted(L, K, *, noise: float, noise_kind: str = "rel", core: str = "normal"
         if noise_kind == "abs":
             scale = float(noise)
         elif noise_kind == "rel":
-            nx = float(np.sqrt(np.dot(X.reshape(-1).astype(np.float64, copy=False),
-                                      X.reshape(-1).astype(np.float64, copy=False)))) \
-                if X.size < (1 << 27) else _norm_chunked(X)
-            ne = float(np.sqrt(np.dot(E.reshape(-1).astype(np.float64, copy=False),
-                                      E.reshape(-1).astype(np.float64, copy=False)))) \
-                if E.size < (1 << 27) else _norm_chunked(E)
+            with _BLAS:
+                nx = float(np.sqrt(np.dot(X.reshape(-1).astype(np.float64, copy=False),
+                                          X.reshape(-1).astype(np.float64, copy=False)))) \
+                    if X.size < (1 << 27) else _norm_chunked(X)
+                ne = float(np.sqrt(np.dot(E.reshape(-1).astype(np.float64, copy=False),
+                                          E.reshape(-1).astype(np.float64, copy=False)))) \
+                    if E.size < (1 << 27) else _norm_chunked(E)
             scale = float(noise) * nx / ne
         else:
             raise ValueError(f"unknown noise kind {noise_kind!r}")
@@ -214,3 +224,22 @@ def batch_shapes(count: int = 512, cfg: int = 5, seed_idx: int = 0,
             K[n] = min(K[n], int(np.prod([K[m] for m in range(N) if m != n])))
         out.append((tuple(L), tuple(K)))
     return out
+
+
+def batch_tensors(shapes, *, noise: float = 1e-3, dtype: str = "f32", cfg: int = 5,
+                  window: int = 32, workers: int = 0):
+    """Yield (i, T_i) for the planted tensors of a batch, in order, drawing up
+    to `window` tensors at a time on a thread pool (each draw is seeded by
+    (cfg, i) alone, so the result does not depend on the pool)."""
+    workers = workers or min(16, os.cpu_count() or 1)
+
+    def one(i):
+        L, K = shapes[i]
+        T, _ = planted(L, K, noise=noise, noise_kind="rel", dtype=dtype, cfg=cfg, idx=i)
+        return T
+
+    with _cf.ThreadPoolExecutor(workers) as ex:
+        for w0 in range(0, len(shapes), window):
+            idx = list(range(w0, min(len(shapes), w0 + window)))
+            for i, T in zip(idx, ex.map(one, idx)):
+                yield i, T
