@@ -189,6 +189,77 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
     }
 }
 
+// Row path through LDS (B == 1): the rows of a wave (64 consecutive a, each a
+// contiguous run of L values) are loaded cooperatively in chunks of
+// kRowLC columns -- eight lanes cover 128 contiguous bytes of one row, so
+// every load instruction reads eight full 128-byte segments -- into a padded
+// LDS tile (pitch kRowLC + 1: conflict-free column reads), then every lane
+// runs the MFMA chain over its own row.  Requires L % 4 == 0 and a base
+// aligned for 16-byte (FP32) or 8-byte (BF16) loads.
+constexpr int kRowLC = 32;
+constexpr int kRowPitch = kRowLC + 1;
+constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  // 4 waves
+// Rows up to this length go through LDS; longer rows are read directly (a
+// lane's eight 16-byte loads then cover 128 contiguous bytes of its row).
+constexpr int kRowLdsMaxL = 64;
+
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
+                                                        const float* __restrict__ F,
+                                                        float* __restrict__ out, int64_t A, int L,
+                                                        int Kt) {
+  extern __shared__ float smem[];
+  float* FT = smem;
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor<KG>(FT, F, L, Kt, k0);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  float* Xs = smem + 4 * L * KG + wave * 64 * kRowPitch;
+  const int64_t row0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int nrows = (int)max((int64_t)0, min((int64_t)64, A - row0));  // rows of this wave
+  const float* ft = FT + (lane & 3) * L * KG;
+
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+  for (int l0 = 0; l0 < L; l0 += kRowLC) {
+    const int lc = min(kRowLC, L - l0);
+    __syncthreads();  // the previous chunk has been consumed (and FT staged)
+    constexpr int kPer = 64 * kRowLC / 4 / 64;  // 16-byte loads per lane
+    f4 v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = lane + 64 * u;
+      const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
+      v[u] = (r < nrows && c < lc) ? load4_f32<NT>(in + (row0 + r) * L + l0 + c)
+                                   : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = lane + 64 * u;
+      const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Xs[r * kRowPitch + c + j] = v[u][j];
+    }
+    __syncthreads();
+    for (int c = 0; c < lc; ++c) {
+      const float x = Xs[lane * kRowPitch + c];
+#pragma unroll
+      for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + c) * KG + g], x, acc[g]);
+    }
+  }
+  if (lane >= nrows) return;
+  float* q = out + (row0 + lane) * Kt;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) q[k] = acc[g][m];
+    }
+}
+
 // ------------------------------------------------------------- BF16 MFMA paths --
 // TK_C_BF16: both operands rounded to bfloat16 (round to nearest even), FP32
 // accumulation, on v_mfma_f32_4x4x4_16b_bf16: the 4x4x1 block structure of the
@@ -645,10 +716,17 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
     hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, C, L, B,
                        K);
   } else if (path == Path::kRows) {
-    const size_t lds = (size_t)16 * L * KG;
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, A, L,
-                       K);
+    if (L <= kRowLdsMaxL) {
+      // short rows: a lane's 16-byte loads would touch one cache segment each
+      const size_t lds = (size_t)16 * L * KG + kRowStageBytes;
+      hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out,
+                         A, L, K);
+    } else {
+      const size_t lds = (size_t)16 * L * KG;
+      hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, A,
+                         L, K);
+    }
   } else {
     const int nb = (int)std::min<int64_t>(B, 256);
     const int na = 256 / nb;
@@ -691,8 +769,12 @@ template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                       float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
-  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
-  int kg = pick_kg(K, std::max(1, (kLdsBudget - 4 * kTileLC * 256) / (16 * L)),
+  Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
+  // LDS beside the factor slice: the staged tile, or the row stage for short rows
+  const int stage = (path == Path::kRows && L <= kRowLdsMaxL) ? (int)kRowStageBytes
+                    : path == Path::kTile                      ? 4 * kTileLC * 256
+                                                               : 0;
+  int kg = pick_kg(K, std::max(1, (kLdsBudget - std::max(stage, 4 * kTileLC * 256)) / (16 * L)),
                    grid_blocks(path, A, B));
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in)
