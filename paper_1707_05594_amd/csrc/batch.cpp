@@ -81,6 +81,12 @@ struct tk_batch {
   EigJob* jobs_warm = nullptr;
   EigJob* jobs_cold = nullptr;
   int n_jobs = 0, Lmax = 0, pmax = 0;
+  // jobs sorted by padded block width: one launch per class, so narrow solves
+  // do not run at the widest width (warm and cold tables share the order)
+  struct EigClass {
+    int job0, count, Lmax, pmax;
+  };
+  std::vector<EigClass> warm_classes, cold_classes;
   float* core = nullptr;
   int64_t* core_off = nullptr;
   double* normG2 = nullptr;
@@ -145,11 +151,11 @@ int enqueue_pass(tk_batch* b) {
     const Launch& l = b->levels[d];
     // items hold indices into the whole node table
     TK_HIP(launch_ttm_grouped(l.in_dtype, b->ttm_nodes, b->ttm_items + l.item0, l.n_items,
-                              b->counters + d, l.Lmax, grid_blocks(b), b->st));
+                              b->counters + d, l.Lmax, grid_blocks(b), d == 0, b->st));
   }
   const Launch& f = b->fold;
   TK_HIP(launch_ttm_grouped(f.in_dtype, b->ttm_nodes, b->ttm_items + f.item0, f.n_items,
-                            b->counters + nl, f.Lmax, grid_blocks(b), b->st));
+                            b->counters + nl, f.Lmax, grid_blocks(b), false, b->st));
   TK_HIP(launch_sumsq_segments(b->core, b->core_off, b->count, b->normG2, b->st));
   TK_HIP(launch_gram_grouped(TK_F32, b->gram, b->gram_items, b->n_gram_items, b->gram_off,
                              b->n_gram, b->gram_total, b->st));
@@ -159,8 +165,9 @@ int enqueue_pass(tk_batch* b) {
 // One HOOI invocation for every tensor: pass, warm eigensolves, factor update.
 int enqueue_iteration(tk_batch* b) {
   if (int rc = enqueue_pass(b)) return rc;
-  TK_HIP(launch_eig(b->n_jobs, b->jobs_warm, 0, b->Lmax, b->pmax, b->S, b->F64a, b->F64b, b->ev,
-                    b->eigwork, b->status, nullptr, 20, 1e-11, b->st));
+  for (const auto& c : b->warm_classes)
+    TK_HIP(launch_eig(c.count, b->jobs_warm, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64b,
+                      b->ev, b->eigwork, b->status, nullptr, 20, 1e-11, b->st));
   TK_HIP(launch_copy_f64(b->F64b, b->F64a, b->nF, b->st));
   TK_HIP(launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, b->st));
   return TK_OK;
@@ -321,8 +328,9 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
   // ---- grouped TTM tables: tree levels, then the folded cores
   std::vector<TtmNodeDesc> nd_h;
   std::vector<int2> it_h;
-  auto add_node = [&](const void* in, float* outp, const float* F, int64_t A, int64_t Ln,
-                      int64_t B, int64_t Kn) {
+  std::vector<int64_t> node_tiles;
+  auto add_node = [&](const void* in, int in_bytes, float* outp, const float* F, int64_t A,
+                      int64_t Ln, int64_t B, int64_t Kn) {
     TtmNodeDesc d;
     d.in = in;
     d.out = outp;
@@ -331,10 +339,12 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     d.B = B;
     d.L = (int)Ln;
     d.K = (int)Kn;
+    d.pad_ = 0;
     int64_t tiles = 0;
-    ttm_tile_geometry(A, B, &d.na, &d.nb, &d.nbt, &tiles);
+    ttm_grouped_geometry(in, outp, in_bytes, A, Ln, B, &d, &tiles);
     const int idx = (int)nd_h.size();
     nd_h.push_back(d);
+    node_tiles.push_back(tiles);
     for (int64_t t = 0; t < tiles; ++t) it_h.push_back(make_int2(idx, (int)t));
   };
   for (int dpt = 0; dpt <= depth_max; ++dpt) {
@@ -351,7 +361,9 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
         int64_t A, Ln, B;
         view(s, nd.pre_mask, nd.mode, &A, &Ln, &B);
         const void* in = nd.parent < 0 ? b->T[i] : (const void*)(b->ws + node_off[i][nd.parent]);
-        add_node(in, b->ws + node_off[i][u], b->Fc + b->fofs[i][nd.mode], A, Ln, B, s.K[nd.mode]);
+        const int in_bytes = (nd.parent < 0 && tdtype == TK_BF16) ? 2 : 4;
+        add_node(in, in_bytes, b->ws + node_off[i][u], b->Fc + b->fofs[i][nd.mode], A, Ln, B,
+                 s.K[nd.mode]);
         b->tree_bytes += (uint64_t)nd.in_card * (nd.parent < 0 && tdtype == TK_BF16 ? 2 : 4) +
                          (uint64_t)nd.out_card * 4;
         l.Lmax = std::max<int>(l.Lmax, (int)Ln);
@@ -374,7 +386,7 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
         if (!nd.is_leaf || nd.mode != m) continue;
         int64_t A, Ln, B;
         view(s, nd.pre_mask, m, &A, &Ln, &B);
-        add_node(b->ws + node_off[i][nd.parent], b->core + core_off_h[i],
+        add_node(b->ws + node_off[i][nd.parent], 4, b->core + core_off_h[i],
                  b->Fc + b->fofs[i][m], A, Ln, B, s.K[m]);
         f.Lmax = std::max<int>(f.Lmax, (int)Ln);
       }
@@ -401,10 +413,13 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     }
     for (const int2& w : it_h) {
       if (w.x < 0 || w.x >= (int)nd_h.size()) return bail(fail(TK_EINVAL, "internal: item node"));
-      const TtmNodeDesc& d = nd_h[w.x];
-      if (w.y < 0 || (int64_t)w.y >= ((d.A + d.na - 1) / d.na) * d.nbt)
+      if (w.y < 0 || (int64_t)w.y >= node_tiles[w.x])
         return bail(fail(TK_EINVAL, "internal: item tile"));
     }
+    for (const TtmNodeDesc& d : nd_h)
+      if ((d.path == kGroupedRows && (d.B != 1 || d.L % 4 != 0 || d.L > 64)) ||
+          (d.path == kGroupedRowsDirect && (d.B != 1 || d.L % 4 != 0)))
+        return bail(fail(TK_EINVAL, "internal: row body on an unsuitable node"));
   }
   if ((rc = upload(&b->ttm_nodes, nd_h, st)) || (rc = upload(&b->ttm_items, it_h, st)) ||
       (rc = dalloc_t(&b->counters, b->levels.size() + 1)))
@@ -490,6 +505,40 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
   for (auto& j : jw)
     if (j.p != j.L) j.p = std::max(j.K, std::min(j.p, j.K + 4));
   for (auto& j : jc) j.V0_off = -1;
+  {
+    // order both tables by the warm block width (stable: ties keep tensor order)
+    std::vector<int> ord(b->n_jobs);
+    for (int q = 0; q < b->n_jobs; ++q) ord[q] = q;
+    auto pad = [](int p) { return (p + 7) / 8 * 8; };
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](int x, int y) { return pad(jw[x].p) < pad(jw[y].p); });
+    std::vector<EigJob> w2, c2;
+    for (int q : ord) {
+      w2.push_back(jw[q]);
+      c2.push_back(jc[q]);
+    }
+    jw.swap(w2);
+    jc.swap(c2);
+    auto classes = [&](const std::vector<EigJob>& js, const std::vector<EigJob>& key,
+                       std::vector<tk_batch::EigClass>* out) {
+      for (int q = 0; q < (int)js.size();) {
+        int r = q;
+        tk_batch::EigClass c{q, 0, 0, 0};
+        while (r < (int)js.size() && pad(key[r].p) == pad(key[q].p)) {
+          c.Lmax = std::max(c.Lmax, js[r].L);
+          c.pmax = std::max(c.pmax, js[r].p);
+          ++r;
+        }
+        c.count = r - q;
+        out->push_back(c);
+        q = r;
+      }
+    };
+    classes(jw, jw, &b->warm_classes);
+    // cold blocks are wider than warm ones: split the cold table at the same
+    // boundaries and take each range's own widest cold block
+    classes(jc, jw, &b->cold_classes);
+  }
   if ((rc = dalloc_t(&b->eigwork, (size_t)work)) || (rc = dalloc_t(&b->status, (size_t)b->n_jobs)) ||
       (rc = upload(&b->jobs_warm, jw, st)) || (rc = upload(&b->jobs_cold, jc, st)))
     return bail(rc);
@@ -517,9 +566,11 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     }
   }
   if (e == hipSuccess) e = launch_fill_int(b->status, b->n_jobs, 0, st);
-  if (e == hipSuccess)
-    e = launch_eig(b->n_jobs, b->jobs_cold, 0, b->Lmax, b->pmax, b->S, b->F64a, b->F64a, b->ev,
+  for (size_t k = 0; k < b->cold_classes.size() && e == hipSuccess; ++k) {
+    const auto& c = b->cold_classes[k];
+    e = launch_eig(c.count, b->jobs_cold, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64a, b->ev,
                    b->eigwork, b->status, nullptr, 100, 1e-11, st);
+  }
   if (e == hipSuccess) e = launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->normT2.data(), b->normT2_dev, sizeof(double) * count,

@@ -16,21 +16,32 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
 int ttm_max_L();
 
 // Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.
+enum { kGroupedTile = 0, kGroupedWide = 1, kGroupedRows = 2, kGroupedRowsDirect = 3 };
 struct TtmNodeDesc {
   const void* in;
   float* out;
   const float* F;  // L x K row-major
   int64_t A, B, nbt;
   int L, K, na, nb;
+  int path;  // kGrouped*: the tile body the node's items run
+  int pad_;
 };
-// Tile geometry of the LDS-staged TTM for a node viewed as [A, L, B].
-void ttm_tile_geometry(int64_t A, int64_t B, int* na, int* nb, int64_t* nbt, int64_t* tiles);
+// Kernel body and item count of a node viewed as [A, L, B] (in_bytes: input
+// element size): the wide body (B % 4 == 0, B >= 16, aligned), the LDS row
+// body (B == 1, L % 4 == 0; through LDS for L <= 64, direct 16-byte row loads
+// above), else the LDS-staged tile body.
+void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_t A, int64_t L,
+                          int64_t B, TtmNodeDesc* d, int64_t* tiles);
+// Dynamic LDS of the grouped kernel for nodes with L <= Lmax.
+size_t ttm_grouped_lds(int Lmax);
 // items: (node, tile) pairs, node an index into `nodes` (the whole table);
 // counter: zeroed device int (the queue head);
 // grid: persistent blocks.  Every node has K <= 16 and L <= Lmax; in_dtype
 // TK_F32 or TK_BF16 for all nodes of the launch.
+// stream_in: the inputs are read once (non-temporal loads).
 hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
-                              int n_items, int* counter, int Lmax, int grid, hipStream_t st);
+                              int n_items, int* counter, int Lmax, int grid, bool stream_in,
+                              hipStream_t st);
 
 // Gram S = Y_(n) Y_(n)^T (gram.hip); `part` holds gram_workspace_elems(L, A*B) doubles
 hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,

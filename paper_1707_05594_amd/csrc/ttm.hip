@@ -59,18 +59,15 @@ __device__ __forceinline__ void stage_factor(float* FT, const float* __restrict_
 // into chunks of 4*KG rows.  NT: the input is streamed (read once, e.g. T at
 // the root), so its loads bypass cache retention.
 template <int KG, typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
-                                                    const float* __restrict__ F,
-                                                    float* __restrict__ out, int64_t C, int L,
-                                                    int64_t B, int Kt) {
-  extern __shared__ float smem[];
-  const int k0 = blockIdx.y * 4 * KG;
+__device__ __forceinline__ void wide_body(const TIn* __restrict__ in, const float* __restrict__ F,
+                                          float* __restrict__ out, int64_t C, int L, int64_t B,
+                                          int Kt, int64_t blk, int k0, float* smem) {
   stage_factor<KG>(smem, F, L, Kt, k0);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t c = ((int64_t)blockIdx.x * 4 + wave) * 256 + 4 * lane;
-  if (((int64_t)blockIdx.x * 4 + wave) * 256 >= C) return;  // whole wave idle
+  const int64_t c = (blk * 4 + wave) * 256 + 4 * lane;
+  if ((blk * 4 + wave) * 256 >= C) return;  // whole wave idle
   const bool active = c < C;
   // lanes past the end read row a = 0 (always in bounds) and store nothing:
   // the loads stay unconditional, so they are issued back to back
@@ -127,6 +124,15 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
     }
 }
 
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t C, int L,
+                                                    int64_t B, int Kt) {
+  extern __shared__ float smem[];
+  wide_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+}
+
 // ------------------------------------------------------------------- row path --
 // B == 1 (the last mode): Out[a, k] = sum_l In[a, l] F[l, k], rows of In
 // contiguous.  Requires L % 4 == 0.  Lane i owns row a = 256*block + thread and
@@ -135,16 +141,13 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
 // lane i is its own row value, the A operands (four k's of row l of F) are
 // the same for every block, so lane i accumulates four k's of its own row.
 template <int KG, typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
-                                                    const float* __restrict__ F,
-                                                    float* __restrict__ out, int64_t A, int L,
-                                                    int Kt) {
-  extern __shared__ float smem[];
-  const int k0 = blockIdx.y * 4 * KG;
+__device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const float* __restrict__ F,
+                                          float* __restrict__ out, int64_t A, int L, int Kt,
+                                          int64_t blk, int k0, float* smem) {
   stage_factor<KG>(smem, F, L, Kt, k0);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t wave_row0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
+  const int64_t wave_row0 = blk * 256 + (threadIdx.x & ~63);
   if (wave_row0 >= A) return;  // whole wave idle
   const int64_t a = wave_row0 + lane;
   const bool active = a < A;
@@ -189,6 +192,15 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
     }
 }
 
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
+                                                    const float* __restrict__ F,
+                                                    float* __restrict__ out, int64_t A, int L,
+                                                    int Kt) {
+  extern __shared__ float smem[];
+  rows_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+}
+
 // Row path through LDS (B == 1): the rows of a wave (64 consecutive a, each a
 // contiguous run of L values) are loaded cooperatively in chunks of
 // kRowLC columns -- eight lanes cover 128 contiguous bytes of one row, so
@@ -204,18 +216,16 @@ constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  /
 constexpr int kRowLdsMaxL = 64;
 
 template <int KG, typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
-                                                        const float* __restrict__ F,
-                                                        float* __restrict__ out, int64_t A, int L,
-                                                        int Kt) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
+                                              const float* __restrict__ F,
+                                              float* __restrict__ out, int64_t A, int L, int Kt,
+                                              int64_t blk, int k0, float* smem) {
   float* FT = smem;
-  const int k0 = blockIdx.y * 4 * KG;
   stage_factor<KG>(FT, F, L, Kt, k0);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   float* Xs = smem + 4 * L * KG + wave * 64 * kRowPitch;
-  const int64_t row0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t row0 = blk * 256 + wave * 64;
   const int nrows = (int)max((int64_t)0, min((int64_t)64, A - row0));  // rows of this wave
   const float* ft = FT + (lane & 3) * L * KG;
 
@@ -258,6 +268,15 @@ __global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ 
       const int k = k0 + 4 * g + m;
       if (k < Kt) q[k] = acc[g][m];
     }
+}
+
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
+                                                        const float* __restrict__ F,
+                                                        float* __restrict__ out, int64_t A, int L,
+                                                        int Kt) {
+  extern __shared__ float smem[];
+  rows_lds_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
 // ------------------------------------------------------------- BF16 MFMA paths --
@@ -511,36 +530,59 @@ __device__ __forceinline__ void tile_body(const TIn* __restrict__ in, const floa
 #pragma unroll
   for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
 
-  for (int l0 = 0; l0 < L; l0 += kTileLC) {
-    const int lc = min(kTileLC, L - l0);
-    __syncthreads();
-    const int total = nav * lc * nbv;
-    // eight loads in flight per thread before the LDS stores
-    for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {
-      float v[8];
-      int dst[8];
+  if (nb >= 64) {
+    // runs of >= 64 consecutive b: thread `col` reads its own column for every
+    // l (for each l the block reads nav runs of nbv consecutive values), all
+    // loads of a chunk in flight, and feeds the MFMAs from registers
+    __syncthreads();  // factor staged
+    const TIn* src = in + ((a0 + a_loc) * L) * B + b0 + b_loc;
+    for (int l0 = 0; l0 < L; l0 += kTileLC) {
+      const int lc = min(kTileLC, L - l0);
+      float v[kTileLC];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256;
-        dst[u] = -1;
-        if (e < total) {
-          const int bb = e % nbv;
-          const int t = e / nbv;
-          const int ll = t % lc;
-          const int aa = t / lc;
-          dst[u] = ll * 256 + aa * nb + bb;
-          v[u] = Elem<TIn>::to_f32(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+      for (int ll = 0; ll < kTileLC; ++ll)
+        v[ll] = (active && ll < lc) ? Elem<TIn>::to_f32(src[(int64_t)(l0 + ll) * B]) : 0.f;
+#pragma unroll
+      for (int ll = 0; ll < kTileLC; ++ll) {
+        if (ll < lc) {
+#pragma unroll
+          for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + ll) * KG + g], v[ll], acc[g]);
         }
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (dst[u] >= 0) X[dst[u]] = v[u];
     }
-    __syncthreads();
-    for (int ll = 0; ll < lc; ++ll) {
-      const float x = active ? X[ll * 256 + col] : 0.f;
+  } else {
+    for (int l0 = 0; l0 < L; l0 += kTileLC) {
+      const int lc = min(kTileLC, L - l0);
+      __syncthreads();
+      const int total = nav * lc * nbv;
+      // short runs: consecutive threads walk b, then l, then a (contiguous
+      // memory for B < nb); eight loads in flight per thread before the stores
+      for (int e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {
+        float v[8];
+        int dst[8];
 #pragma unroll
-      for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + ll) * KG + g], x, acc[g]);
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u * 256;
+          dst[u] = -1;
+          if (e < total) {
+            const int bb = e % nbv;
+            const int t = e / nbv;
+            const int ll = t % lc;
+            const int aa = t / lc;
+            dst[u] = ll * 256 + aa * nb + bb;
+            v[u] = Elem<TIn>::to_f32(in[((a0 + aa) * L + (l0 + ll)) * B + b0 + bb]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (dst[u] >= 0) X[dst[u]] = v[u];
+      }
+      __syncthreads();
+      for (int ll = 0; ll < lc; ++ll) {
+        const float x = active ? X[ll * 256 + col] : 0.f;
+#pragma unroll
+        for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + ll) * KG + g], x, acc[g]);
+      }
     }
   }
   if (!active) return;
@@ -568,7 +610,7 @@ __global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
 // from a device queue by a persistent grid.  Each block takes the next item
 // with one atomic increment; every block leaves once the queue is empty.
 // Nodes have K <= 16 (one K-chunk of four groups) and L <= Lmax.
-template <typename TIn>
+template <typename TIn, bool NT>
 __global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict__ nodes,
                                                    const int2* __restrict__ items, int n_items,
                                                    int* __restrict__ counter) {
@@ -582,8 +624,15 @@ __global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict
     if (it >= n_items) break;
     const int2 w = items[it];
     const TtmNodeDesc d = nodes[w.x];
-    tile_body<4, TIn>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.B, d.K, d.na, d.nb, d.nbt, w.y, 0,
-                      smem);
+    if (d.path == kGroupedWide)
+      wide_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedRows)
+      rows_lds_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedRowsDirect)
+      rows_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    else
+      tile_body<4, TIn>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.B, d.K, d.na, d.nb, d.nbt, w.y,
+                        0, smem);
   }
 }
 
@@ -862,24 +911,52 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 
 }  // namespace
 
-void ttm_tile_geometry(int64_t A, int64_t B, int* na, int* nb, int64_t* nbt, int64_t* tiles) {
-  *nb = (int)std::min<int64_t>(B, 256);
-  *na = 256 / *nb;
-  *nbt = (B + *nb - 1) / *nb;
-  *tiles = ((A + *na - 1) / *na) * *nbt;
+void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_t A, int64_t L,
+                          int64_t B, TtmNodeDesc* d, int64_t* tiles) {
+  const bool in_al = (uintptr_t)in % (4 * (uintptr_t)in_bytes) == 0;
+  d->nb = (int)std::min<int64_t>(B, 256);
+  d->na = 256 / d->nb;
+  d->nbt = (B + d->nb - 1) / d->nb;
+  if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) {
+    d->path = kGroupedWide;  // 1024 columns per item
+    *tiles = (A * B + 1023) / 1024;
+  } else if (B == 1 && L % 4 == 0 && in_al) {
+    d->path = L <= kRowLdsMaxL ? kGroupedRows : kGroupedRowsDirect;  // 256 rows per item
+    *tiles = (A + 255) / 256;
+  } else {
+    d->path = kGroupedTile;
+    *tiles = ((A + d->na - 1) / d->na) * d->nbt;
+  }
+}
+
+size_t ttm_grouped_lds(int Lmax) {
+  const size_t factor = (size_t)16 * Lmax * 4;
+  const size_t rows = (size_t)16 * std::min(Lmax, kRowLdsMaxL) * 4 + kRowStageBytes;
+  return std::max(factor + (size_t)4 * kTileLC * 256, rows);
 }
 
 hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
-                              int n_items, int* counter, int Lmax, int grid, hipStream_t st) {
+                              int n_items, int* counter, int Lmax, int grid, bool stream_in,
+                              hipStream_t st) {
   if (n_items == 0) return hipSuccess;
-  const size_t lds = (size_t)16 * Lmax * 4 + (size_t)4 * kTileLC * 256;
+  const size_t lds = ttm_grouped_lds(Lmax);
+  if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
   grid = std::max(1, std::min(grid, n_items));
-  if (in_dtype == TK_F32)
-    hipLaunchKernelGGL(ttm_grouped<float>, dim3(grid), dim3(256), lds, st, nodes, items, n_items,
-                       counter);
-  else
-    hipLaunchKernelGGL(ttm_grouped<uint16_t>, dim3(grid), dim3(256), lds, st, nodes, items,
-                       n_items, counter);
+#define TK_GROUPED(T, NT_)                                                                \
+  hipLaunchKernelGGL((ttm_grouped<T, NT_>), dim3(grid), dim3(256), lds, st, nodes, items, \
+                     n_items, counter)
+  if (in_dtype == TK_F32) {
+    if (stream_in)
+      TK_GROUPED(float, true);
+    else
+      TK_GROUPED(float, false);
+  } else {
+    if (stream_in)
+      TK_GROUPED(uint16_t, true);
+    else
+      TK_GROUPED(uint16_t, false);
+  }
+#undef TK_GROUPED
   return hipGetLastError();
 }
 
