@@ -16,7 +16,13 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
 int ttm_max_L();
 
 // Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.
-enum { kGroupedTile = 0, kGroupedWide = 1, kGroupedRows = 2, kGroupedRowsDirect = 3 };
+enum {
+  kGroupedTile = 0,
+  kGroupedWide = 1,
+  kGroupedRows = 2,        // B == 1 through LDS, 16-byte loads (L % 4 == 0, L <= 64)
+  kGroupedRowsDirect = 3,  // B == 1, direct 16-byte row loads (L % 4 == 0, L > 64)
+  kGroupedRowsScalar = 4   // B == 1 through LDS, one element per load
+};
 struct TtmNodeDesc {
   const void* in;
   float* out;

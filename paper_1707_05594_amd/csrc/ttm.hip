@@ -206,8 +206,8 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
 // kRowLC columns -- eight lanes cover 128 contiguous bytes of one row, so
 // every load instruction reads eight full 128-byte segments -- into a padded
 // LDS tile (pitch kRowLC + 1: conflict-free column reads), then every lane
-// runs the MFMA chain over its own row.  Requires L % 4 == 0 and a base
-// aligned for 16-byte (FP32) or 8-byte (BF16) loads.
+// runs the MFMA chain over its own row.  V4: 16-byte loads (L % 4 == 0 and a
+// base aligned for them); otherwise one element per load, 32 in flight.
 constexpr int kRowLC = 32;
 constexpr int kRowPitch = kRowLC + 1;
 constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  // 4 waves
@@ -215,7 +215,7 @@ constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  /
 // lane's eight 16-byte loads then cover 128 contiguous bytes of its row).
 constexpr int kRowLdsMaxL = 64;
 
-template <int KG, typename TIn, bool NT>
+template <int KG, typename TIn, bool NT, bool V4>
 __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
                                               const float* __restrict__ F,
                                               float* __restrict__ out, int64_t A, int L, int Kt,
@@ -236,21 +236,37 @@ __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
   for (int l0 = 0; l0 < L; l0 += kRowLC) {
     const int lc = min(kRowLC, L - l0);
     __syncthreads();  // the previous chunk has been consumed (and FT staged)
-    constexpr int kPer = 64 * kRowLC / 4 / 64;  // 16-byte loads per lane
-    f4 v[kPer];
+    if constexpr (V4) {
+      constexpr int kPer = 64 * kRowLC / 4 / 64;  // 16-byte loads per lane
+      f4 v[kPer];
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int q = lane + 64 * u;
-      const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
-      v[u] = (r < nrows && c < lc) ? load4_f32<NT>(in + (row0 + r) * L + l0 + c)
-                                   : f4{0.f, 0.f, 0.f, 0.f};
-    }
+      for (int u = 0; u < kPer; ++u) {
+        const int q = lane + 64 * u;
+        const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
+        v[u] = (r < nrows && c < lc) ? load4_f32<NT>(in + (row0 + r) * L + l0 + c)
+                                     : f4{0.f, 0.f, 0.f, 0.f};
+      }
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int q = lane + 64 * u;
-      const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
+      for (int u = 0; u < kPer; ++u) {
+        const int q = lane + 64 * u;
+        const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Xs[r * kRowPitch + c + j] = v[u][j];
+        for (int j = 0; j < 4; ++j) Xs[r * kRowPitch + c + j] = v[u][j];
+      }
+    } else {
+      constexpr int kPer = 64 * kRowLC / 64;  // one element per load
+      float v[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int q = lane + 64 * u;
+        const int r = q / kRowLC, c = q % kRowLC;
+        v[u] = (r < nrows && c < lc) ? Elem<TIn>::to_f32(in[(row0 + r) * L + l0 + c]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int q = lane + 64 * u;
+        Xs[(q / kRowLC) * kRowPitch + q % kRowLC] = v[u];
+      }
     }
     __syncthreads();
     for (int c = 0; c < lc; ++c) {
@@ -270,13 +286,13 @@ __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
     }
 }
 
-template <int KG, typename TIn, bool NT>
+template <int KG, typename TIn, bool NT, bool V4>
 __global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
                                                         const float* __restrict__ F,
                                                         float* __restrict__ out, int64_t A, int L,
                                                         int Kt) {
   extern __shared__ float smem[];
-  rows_lds_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+  rows_lds_body<KG, TIn, NT, V4>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
 // ------------------------------------------------------------- BF16 MFMA paths --
@@ -627,7 +643,9 @@ __global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict
     if (d.path == kGroupedWide)
       wide_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0, smem);
     else if (d.path == kGroupedRows)
-      rows_lds_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+      rows_lds_body<4, TIn, NT, true>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedRowsScalar)
+      rows_lds_body<4, TIn, NT, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
     else if (d.path == kGroupedRowsDirect)
       rows_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
     else
@@ -707,7 +725,7 @@ template <typename TIn>
 Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
   const bool in_al = (uintptr_t)in % (4 * sizeof(TIn)) == 0;
   if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) return Path::kWide;
-  if (B == 1 && L % 4 == 0 && in_al) return Path::kRows;
+  if (B == 1) return Path::kRows;  // direct, or staged through LDS (short or unaligned rows)
   return Path::kTile;
 }
 
@@ -766,11 +784,17 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
                        K);
   } else if (path == Path::kRows) {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
-    if (L <= kRowLdsMaxL) {
-      // short rows: a lane's 16-byte loads would touch one cache segment each
+    const bool v4 = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+    if (!v4 || L <= kRowLdsMaxL) {
+      // short rows (a lane's 16-byte loads would touch one cache segment each)
+      // or rows that cannot be read 16 bytes at a time: staged through LDS
       const size_t lds = (size_t)16 * L * KG + kRowStageBytes;
-      hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out,
-                         A, L, K);
+      if (v4)
+        hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT, true>), grid, dim3(256), lds, st, in,
+                           F, out, A, L, K);
+      else
+        hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT, false>), grid, dim3(256), lds, st, in,
+                           F, out, A, L, K);
     } else {
       const size_t lds = (size_t)16 * L * KG;
       hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, A,
@@ -820,7 +844,12 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
   Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
   // LDS beside the factor slice: the staged tile, or the row stage for short rows
-  const int stage = (path == Path::kRows && L <= kRowLdsMaxL) ? (int)kRowStageBytes
+  const bool rows_v4 = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+  // rows staged through LDS need the stage beside one K-group at least
+  if (path == Path::kRows && (L <= kRowLdsMaxL || !rows_v4) &&
+      (size_t)16 * L + kRowStageBytes > (size_t)kLdsBudget)
+    path = Path::kTile;
+  const int stage = (path == Path::kRows && (L <= kRowLdsMaxL || !rows_v4)) ? (int)kRowStageBytes
                     : path == Path::kTile                      ? 4 * kTileLC * 256
                                                                : 0;
   int kg = pick_kg(K, std::max(1, (kLdsBudget - std::max(stage, 4 * kTileLC * 256)) / (16 * L)),
@@ -880,7 +909,10 @@ template <typename TIn>
 hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                        float* out, bool stream_in, bool x3, int tile, hipStream_t st) {
   const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
-  if (path == Path::kTile) return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, tile, st);
+  // the BF16 row kernel reads four consecutive l per lane: L % 4 == 0, aligned
+  const bool rows_ok = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+  if (path == Path::kTile || (path == Path::kRows && !rows_ok))
+    return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, tile, st);
   const int per_group = 32 * ((L + 3) / 4) * (x3 ? 2 : 1);  // LDS bytes per K-group
   int kg_cap = std::max(1, kLdsBudget / per_group);
   if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
@@ -911,6 +943,10 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 
 }  // namespace
 
+// Longest rows the grouped kernel stages through LDS (factor slice of four
+// K-groups plus the row stage within the LDS budget).
+constexpr int kGroupedRowStageMaxL = (int)((kLdsBudget - kRowStageBytes) / (16 * 4));
+
 void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_t A, int64_t L,
                           int64_t B, TtmNodeDesc* d, int64_t* tiles) {
   const bool in_al = (uintptr_t)in % (4 * (uintptr_t)in_bytes) == 0;
@@ -920,8 +956,12 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
   if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) {
     d->path = kGroupedWide;  // 1024 columns per item
     *tiles = (A * B + 1023) / 1024;
-  } else if (B == 1 && L % 4 == 0 && in_al) {
-    d->path = L <= kRowLdsMaxL ? kGroupedRows : kGroupedRowsDirect;  // 256 rows per item
+  } else if (B == 1 && ((L % 4 == 0 && in_al) || L <= kGroupedRowStageMaxL)) {
+    // 256 rows per item: through LDS (16-byte or single loads) or direct
+    if (L % 4 == 0 && in_al)
+      d->path = L <= kRowLdsMaxL ? kGroupedRows : kGroupedRowsDirect;
+    else
+      d->path = kGroupedRowsScalar;
     *tiles = (A + 255) / 256;
   } else {
     d->path = kGroupedTile;
@@ -931,7 +971,7 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
 
 size_t ttm_grouped_lds(int Lmax) {
   const size_t factor = (size_t)16 * Lmax * 4;
-  const size_t rows = (size_t)16 * std::min(Lmax, kRowLdsMaxL) * 4 + kRowStageBytes;
+  const size_t rows = (size_t)16 * std::min(Lmax, kGroupedRowStageMaxL) * 4 + kRowStageBytes;
   return std::max(factor + (size_t)4 * kTileLC * 256, rows);
 }
 
