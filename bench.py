@@ -16,6 +16,8 @@ Prints ONE JSON line.  Extra objects:
   cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
                   host for a bounded sample: one HOOI invocation of the same
                   tensor.
+  c3_bf16_storage -- the 80^5 rank-10 tensor stored as BF16, HOOI with FP32,
+                  bf16x3 and BF16 TTMs (precision study), FP64 residual errors.
   batch        -- batched HOOI over 512 planted 3- and 4-mode tensors (grouped
                   persistent TTM levels in a replayed HIP graph).
   mixed        -- the same HOOI with T stored as BF16, TTMs in bf16x3 and in
@@ -118,6 +120,48 @@ def cpu_baseline(T32, K, F0):
                 seconds=round(dt, 2))
 
 
+def c3_leg(steps, warmup):
+    """The five-mode 80^5 tensor stored as BF16 (rank 10, 1e-2 relative noise):
+    HOOI iterations/s with FP32, bf16x3 and BF16 TTMs, each run's error by the
+    FP64 explicit residual against the stored tensor."""
+    import torch
+
+    import paper_1707_05594_amd as tk
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    T, info = synth.workload("planted_80x80x80x80x80_r10_bf16")
+    K = info["K"]
+    Td = torch.from_numpy(T.view("int16")).view(torch.bfloat16).to(dev)
+    del T
+    torch.cuda.synchronize()
+    log(f"c3: generated 80^5 BF16 in {time.perf_counter() - t0:.1f}s")
+    plan = tk.ttm_tree_plan(info["L"], K)
+    res = {"workload": "planted 80x80x80x80x80 stored BF16, Tucker rank 10/mode, 1e-2 rel noise, "
+                       "HOSVD start, DP-optimal TTM-tree", "tree": plan.string(),
+           "tree_macs": plan.cost()}
+    F0 = None
+    for compute in ("fp32", "bf16x3", "bf16"):
+        ctx = tk.hooi_init(Td, K, plan=plan, compute=compute, F0=F0)
+        if F0 is None:
+            F0 = ctx.factors()
+        ctx.iterate(max(1, warmup))
+        ctx.set_factors(F0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        errs = ctx.iterate(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / steps
+        res[compute] = {"value": round(1.0 / dt, 3), "unit": "HOOI iters/s",
+                        "ms_per_step": round(1e3 * dt, 4), "rel_err": errs[-1],
+                        "rel_err_explicit": ctx.error_explicit()}
+        log(f"c3 {compute}: {res[compute]['value']} it/s, error {res[compute]['rel_err_explicit']:.6e}")
+        del ctx
+    del Td
+    torch.cuda.empty_cache()
+    return res
+
+
 def batch_leg(steps, warmup, seq_count=64):
     """Batched HOOI over the uneven 512-tensor batch (3- or 4-mode, L in
     [32, 128], K in [4, 16], 1e-3 relative noise, FP32): iterations/s of the
@@ -202,6 +246,7 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
+    ap.add_argument("--skip-c3", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
                          "(reference dispatches for HBM counter calibration)")
@@ -301,6 +346,9 @@ def main():
             del ctxb
         out["mixed"] = mixed
         del Tb
+
+    if not args.skip_c3:
+        out["c3_bf16_storage"] = c3_leg(args.steps, args.warmup)
 
     if not args.skip_batch:
         out["batch"] = batch_leg(args.steps, args.warmup)
