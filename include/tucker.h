@@ -137,7 +137,10 @@ void tk_plan_free(tk_plan* plan);
  *          modes the TTMs that form the core (the tree path to the leaf
  *          that folds it, and the direct core chain) run at FP32: the error
  *          is ||T||^2 - ||G||^2, so ||G||^2 needs more than BF16 accuracy.
- *          Intermediates are stored FP32 in every non-FP64 mode.
+ *          Intermediates are stored FP32, except in TK_C_BF16 mode where a
+ *          node whose children are all TTMs run by a BF16 kernel stores its
+ *          output as BF16 (those children round their input to BF16 anyway);
+ *          leaf tensors, which the Grams read, stay FP32.
  *   F0_host: NULL to start from HOSVD (F_n = leading K_n left singular vectors
  *          of T_(n)), or host FP64 factors F_0..F_{N-1} concatenated, each
  *          L_n x K_n row-major (checkpoint / resume).  Copied.

@@ -64,6 +64,15 @@ struct tk_ctx {
   int core_compute = TK_C_FP32;
   std::vector<int> node_compute;  // per tree node: compute, or core_compute on the fold path
   std::vector<int> node_tile;     // per tree node: TK_TILE_* kernel choice from the plan
+  // per tree node: storage type of its output.  In TK_C_BF16 mode nodes off the
+  // fold path whose kernel is a BF16 one and whose children are all TTMs write
+  // BF16 (those consumers round their input to BF16 anyway); everything else,
+  // leaf tensors included, is stored in wdtype.
+  std::vector<int> node_out_dt;
+  int in_dtype_of(int u) const {
+    const int p = tree.nodes[u].parent;
+    return p < 0 ? tdtype : node_out_dt[p];
+  }
   int wdtype = TK_F32;  // element type of intermediates and compute-precision factors
   const void* T = nullptr;
   hipStream_t st = nullptr;
@@ -298,14 +307,15 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
     // which the pending solve of that mode may still read)
     if (int rc = wait_factor(c, nd.mode)) return rc;
     const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
-    const int in_dt = nd.parent < 0 ? c->tdtype : c->wdtype;
+    const int in_dt = c->in_dtype_of(u);
     int64_t A, L, B;
     view(s, nd.pre_mask, nd.mode, &A, &L, &B);
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
     if (!nd.is_leaf) {
       // children of the root stream T (too large to stay in cache between them)
       TK_HIP(launch_ttm(in_dt, c->node_compute[u], in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
-                        c->wsp(c->node_off[u]), c->st, nd.parent < 0, c->node_tile[u]));
+                        c->wsp(c->node_off[u]), c->st, nd.parent < 0, c->node_tile[u],
+                        c->node_out_dt[u]));
     } else {
       const int n = nd.mode;
       TK_HIP(launch_gram(in_dt, in, A, L, B, c->S + c->sofs[n], c->gpart, c->st));
@@ -555,6 +565,39 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   if (c->wdtype == TK_F64) {  // the FP64 masters double as compute copies
     c->Fc = c->F64a;
     c->Fcb = c->F64b;
+  }
+  // output storage per node, parents before children (a child's kernel choice
+  // depends on its input's type).  A node whose output is a leaf tensor keeps
+  // it in wdtype: the Gram reads the leaf unrounded.
+  std::vector<char> feeds_leaf(nodes.size(), 0);
+  for (const tk_node& nd : nodes)
+    if (nd.is_leaf && nd.parent >= 0) feeds_leaf[nd.parent] = 1;
+  c->node_out_dt.assign(nodes.size(), -1);
+  for (size_t u0 = 0; u0 < nodes.size(); ++u0) {
+    std::vector<int> up;
+    for (int v = (int)u0; v >= 0 && c->node_out_dt[v] < 0; v = nodes[v].parent) up.push_back(v);
+    for (auto it = up.rbegin(); it != up.rend(); ++it) {
+      const int u = *it;
+      const tk_node& nd = nodes[u];
+      int dt = c->wdtype;
+      if (!nd.is_leaf && !feeds_leaf[u] && c->node_compute[u] == TK_C_BF16) {
+        int64_t A, Lu, B;
+        view(s, nd.pre_mask, nd.mode, &A, &Lu, &B);
+        const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
+        bool ok = ttm_bf16_output_ok(c->in_dtype_of(u), TK_C_BF16, in, Lu, B,
+                                     c->wsp(c->node_off[u]), c->node_tile[u]);
+        for (size_t v = 0; v < nodes.size() && ok; ++v) {
+          if (nodes[v].parent != u) continue;
+          int64_t Av, Lv, Bv;
+          view(s, nodes[v].pre_mask, nodes[v].mode, &Av, &Lv, &Bv);
+          ok = c->node_compute[v] == TK_C_BF16 &&
+               ttm_bf16_output_ok(TK_BF16, TK_C_BF16, c->wsp(c->node_off[u]), Lv, Bv,
+                                  c->wsp(c->node_off[v]), c->node_tile[v]);
+        }
+        if (ok) dt = TK_BF16;
+      }
+      c->node_out_dt[u] = dt;
+    }
   }
 
   {
@@ -810,10 +853,10 @@ extern "C" int tk_get_leaf(tk_ctx* c, int n, double* host) {
   if (n < 0 || n >= c->s.N) return fail(TK_EINVAL, "mode %d out of range", n);
   if (c->leaves.empty()) return fail(TK_EINVAL, "call tk_tree_pass first");
   const int64_t m = c->leaf_elems[n];
-  // the leaf's parent is T itself only when N == 2 and the leaf hangs off the root
+  // a leaf holds its parent's output type (T's own when it hangs off the root)
   int dt = c->wdtype;
-  for (const tk_node& nd : c->tree.nodes)
-    if (nd.is_leaf && nd.mode == n && nd.parent < 0) dt = c->tdtype;
+  for (size_t u = 0; u < c->tree.nodes.size(); ++u)
+    if (c->tree.nodes[u].is_leaf && c->tree.nodes[u].mode == n) dt = c->in_dtype_of((int)u);
   if (dt == TK_F64) {
     TK_HIP(hipMemcpy(host, c->leaves[n], sizeof(double) * m, hipMemcpyDeviceToHost));
   } else if (dt == TK_F32) {

@@ -9,10 +9,14 @@ namespace tk {
 
 // TTM node: Out[a,k,b] = sum_l F[l,k] In[a,l,b]  (ttm.hip)
 // stream_in: the input is read once (streamed past the caches)
-// tile: TK_TILE_* kernel choice (FP64 compute ignores it)
+// tile: TK_TILE_* kernel choice (FP64 compute ignores it).  out_dtype: TK_F32
+// (TK_F64 for FP64 compute), or TK_BF16 for TK_C_BF16 nodes for which
+// ttm_bf16_output_ok() holds (the node runs a BF16 kernel).
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
                       const void* F, int64_t K, void* out, hipStream_t st,
-                      bool stream_in = false, int tile = 0);
+                      bool stream_in = false, int tile = 0, int out_dtype = TK_F32);
+bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t L, int64_t B,
+                        const void* out, int tile);
 int ttm_max_L();
 
 // Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.

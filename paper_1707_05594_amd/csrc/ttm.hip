@@ -376,10 +376,10 @@ __device__ __forceinline__ void wide_bf16_block(f4 (&acc)[KG][4], const f4 (&x)[
 }
 
 // Wide path (B % 4 == 0): lane owns columns c0 + 4i .. c0 + 4i + 3.
-template <int KG, typename TIn, bool NT, bool X3>
+template <int KG, typename TIn, bool NT, bool X3, bool OutBF16>
 __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
                                                      const float* __restrict__ F,
-                                                     float* __restrict__ out, int64_t C, int L,
+                                                     void* __restrict__ out_, int64_t C, int L,
                                                      int64_t B, int Kt) {
   extern __shared__ uint2 sfb[];
   const int LB = (L + 3) / 4;
@@ -431,15 +431,21 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
     wide_bf16_block<KG, X3, kSplitIn>(acc, x, fh + lb * KG, fl + lb * KG);
   }
   if (!active) return;
-  float* q = out + (a * Kt) * B + b;
+  const int64_t q0 = (a * Kt) * B + b;
 #pragma unroll
   for (int g = 0; g < KG; ++g)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int k = k0 + 4 * g + m;
       if (k < Kt) {
-        f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
-        *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
+        if constexpr (OutBF16) {
+          // BF16 output (rounded as the next BF16 node would round it on load)
+          uint2 v = {pack_bf16(acc[g][0][m], acc[g][1][m]), pack_bf16(acc[g][2][m], acc[g][3][m])};
+          *reinterpret_cast<uint2*>((uint16_t*)out_ + q0 + (int64_t)k * B) = v;
+        } else {
+          f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
+          *reinterpret_cast<f4*>((float*)out_ + q0 + (int64_t)k * B) = v;
+        }
       }
     }
 }
@@ -462,10 +468,10 @@ __device__ __forceinline__ void rows_bf16_block(f4 (&acc)[KG], const f4 x, const
 
 // Row path (B == 1, L % 4 == 0): lane owns row a; four consecutive l of its
 // row form one MFMA operand as loaded.
-template <int KG, typename TIn, bool NT, bool X3>
+template <int KG, typename TIn, bool NT, bool X3, bool OutBF16>
 __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
                                                      const float* __restrict__ F,
-                                                     float* __restrict__ out, int64_t A, int L,
+                                                     void* __restrict__ out_, int64_t A, int L,
                                                      int Kt) {
   extern __shared__ uint2 sfb[];
   const int LB = L / 4;
@@ -502,13 +508,17 @@ __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
   for (; lb < LB; ++lb)
     rows_bf16_block<KG, X3, kSplitIn>(acc, load4_f32<NT>(p + 4 * lb), fh + lb * KG, fl + lb * KG);
   if (!active) return;
-  float* q = out + a * Kt;
 #pragma unroll
   for (int g = 0; g < KG; ++g)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int k = k0 + 4 * g + m;
-      if (k < Kt) q[k] = acc[g][m];
+      if (k < Kt) {
+        if constexpr (OutBF16)
+          ((__bf16*)out_)[a * Kt + k] = (__bf16)acc[g][m];
+        else
+          ((float*)out_)[a * Kt + k] = acc[g][m];
+      }
     }
 }
 
@@ -864,66 +874,85 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
 // wide kernel (it spills); wider K is covered by more chunks.
 constexpr int kWideBf16MaxKG = 12;
 
-template <typename TIn, int KG, bool NT, bool X3>
+template <typename TIn, int KG, bool NT, bool X3, bool OutBF16>
 hipError_t launch_bf16_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
-                          int K, float* out, hipStream_t st) {
+                          int K, void* out, hipStream_t st) {
   const int chunks = (K + 4 * KG - 1) / (4 * KG);
   const size_t lds = (size_t)32 * ((L + 3) / 4) * KG * (X3 ? 2 : 1);
   if (path == Path::kWide) {
     if constexpr (KG <= kWideBf16MaxKG) {
       const int64_t C = A * B;
       dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
-      hipLaunchKernelGGL((ttm_wide_bf16<KG, TIn, NT, X3>), grid, dim3(256), lds, st, in, F, out,
+      hipLaunchKernelGGL((ttm_wide_bf16<KG, TIn, NT, X3, OutBF16>), grid, dim3(256), lds, st, in,
+                         F, out,
                          C, L, B, K);
     } else {
       return hipErrorInvalidValue;  // not reached: launch_bf16 caps the wide KG
     }
   } else {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_rows_bf16<KG, TIn, NT, X3>), grid, dim3(256), lds, st, in, F, out,
+    hipLaunchKernelGGL((ttm_rows_bf16<KG, TIn, NT, X3, OutBF16>), grid, dim3(256), lds, st, in, F,
+                       out,
                        A, L, K);
   }
   return hipGetLastError();
 }
 
-template <typename TIn, bool NT, bool X3>
+template <typename TIn, bool NT, bool X3, bool OutBF16>
 hipError_t launch_bf16_nt(Path path, int kg, const TIn* in, int64_t A, int L, int64_t B,
-                          const float* F, int K, float* out, hipStream_t st) {
+                          const float* F, int K, void* out, hipStream_t st) {
   switch (kg) {
-    case 1: return launch_bf16_kg<TIn, 1, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 2: return launch_bf16_kg<TIn, 2, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 3: return launch_bf16_kg<TIn, 3, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 4: return launch_bf16_kg<TIn, 4, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 5: return launch_bf16_kg<TIn, 5, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 6: return launch_bf16_kg<TIn, 6, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 8: return launch_bf16_kg<TIn, 8, NT, X3>(path, in, A, L, B, F, K, out, st);
-    case 12: return launch_bf16_kg<TIn, 12, NT, X3>(path, in, A, L, B, F, K, out, st);
-    default: return launch_bf16_kg<TIn, 16, NT, X3>(path, in, A, L, B, F, K, out, st);
+    case 1: return launch_bf16_kg<TIn, 1, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 2: return launch_bf16_kg<TIn, 2, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 3: return launch_bf16_kg<TIn, 3, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 4: return launch_bf16_kg<TIn, 4, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 5: return launch_bf16_kg<TIn, 5, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 6: return launch_bf16_kg<TIn, 6, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 8: return launch_bf16_kg<TIn, 8, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 12: return launch_bf16_kg<TIn, 12, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    default: return launch_bf16_kg<TIn, 16, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
   }
 }
 
 // BF16 / split-BF16 compute.  Nodes that need the tile path (B not a multiple
 // of four, or B == 1 with L not a multiple of four) run the FP32 tile kernel:
 // at least as accurate as the mode asks for.
+// True when a TK_C_BF16 node with these operands runs a BF16 kernel (wide or
+// row), which can also write its output in BF16.
+template <typename TIn>
+bool bf16_kernel_applies(const TIn* in, const void* out, int64_t L, int64_t B, int tile) {
+  if (tile == TK_TILE_STAGED) return false;
+  const Path path = choose_path(in, (const float*)out, L, B);
+  const bool rows_ok = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+  return path == Path::kWide || (path == Path::kRows && rows_ok);
+}
+
 template <typename TIn>
 hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
-                       float* out, bool stream_in, bool x3, int tile, hipStream_t st) {
-  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
+                       void* out, bool stream_in, bool x3, bool out_bf16, int tile,
+                       hipStream_t st) {
+  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, (float*)out, L, B);
   // the BF16 row kernel reads four consecutive l per lane: L % 4 == 0, aligned
-  const bool rows_ok = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
-  if (path == Path::kTile || (path == Path::kRows && !rows_ok))
-    return launch_f32<TIn>(in, A, L, B, F, K, out, stream_in, tile, st);
+  if (!bf16_kernel_applies(in, out, L, B, tile)) {
+    if (out_bf16) return hipErrorInvalidValue;  // callers ask for BF16 output only here
+    return launch_f32<TIn>(in, A, L, B, F, K, (float*)out, stream_in, tile, st);
+  }
+  if (out_bf16 && x3) return hipErrorInvalidValue;
   const int per_group = 32 * ((L + 3) / 4) * (x3 ? 2 : 1);  // LDS bytes per K-group
   int kg_cap = std::max(1, kLdsBudget / per_group);
   if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
   int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in) {
-    if (x3) return launch_bf16_nt<TIn, true, true>(path, kg, in, A, L, B, F, K, out, st);
-    return launch_bf16_nt<TIn, true, false>(path, kg, in, A, L, B, F, K, out, st);
+    if (x3) return launch_bf16_nt<TIn, true, true, false>(path, kg, in, A, L, B, F, K, out, st);
+    if (out_bf16)
+      return launch_bf16_nt<TIn, true, false, true>(path, kg, in, A, L, B, F, K, out, st);
+    return launch_bf16_nt<TIn, true, false, false>(path, kg, in, A, L, B, F, K, out, st);
   }
-  if (x3) return launch_bf16_nt<TIn, false, true>(path, kg, in, A, L, B, F, K, out, st);
-  return launch_bf16_nt<TIn, false, false>(path, kg, in, A, L, B, F, K, out, st);
+  if (x3) return launch_bf16_nt<TIn, false, true, false>(path, kg, in, A, L, B, F, K, out, st);
+  if (out_bf16)
+    return launch_bf16_nt<TIn, false, false, true>(path, kg, in, A, L, B, F, K, out, st);
+  return launch_bf16_nt<TIn, false, false, false>(path, kg, in, A, L, B, F, K, out, st);
 }
 
 template <int KC>
@@ -1003,9 +1032,19 @@ hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2
 // Largest L the TTM kernels accept (factor slice of at least one K-group in LDS).
 int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }
 
+bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t L, int64_t B,
+                        const void* out, int tile) {
+  if (compute != TK_C_BF16) return false;
+  if (in_dtype == TK_F32) return bf16_kernel_applies((const float*)in, out, L, B, tile);
+  if (in_dtype == TK_BF16) return bf16_kernel_applies((const uint16_t*)in, out, L, B, tile);
+  return false;
+}
+
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
                       const void* F, int64_t K, void* out, hipStream_t st, bool stream_in,
-                      int tile) {
+                      int tile, int out_dtype) {
+  if (out_dtype == TK_BF16 && !ttm_bf16_output_ok(in_dtype, compute, in, L, B, out, tile))
+    return hipErrorInvalidValue;
   if (A * B == 0 || K == 0) return hipSuccess;
   if (compute == TK_C_FP64) {
     const int Li = (int)L;
@@ -1021,11 +1060,12 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   }
   if (compute == TK_C_BF16 || compute == TK_C_BF16X3) {
     const bool x3 = compute == TK_C_BF16X3;
+    const bool ob = out_dtype == TK_BF16;
     if (in_dtype == TK_F32)
-      return launch_bf16<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
-                                (float*)out, stream_in, x3, tile, st);
-    return launch_bf16<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
-                                 (float*)out, stream_in, x3, tile, st);
+      return launch_bf16<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K, out,
+                                stream_in, x3, ob, tile, st);
+    return launch_bf16<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K, out,
+                                 stream_in, x3, ob, tile, st);
   }
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
