@@ -23,9 +23,11 @@ int ttm_max_L();
 enum {
   kGroupedTile = 0,
   kGroupedWide = 1,
-  kGroupedRows = 2,        // B == 1 through LDS, 16-byte loads (L % 4 == 0, L <= 64)
-  kGroupedRowsDirect = 3,  // B == 1, direct 16-byte row loads (L % 4 == 0, L > 64)
+  kGroupedRows = 2,        // B == 1 through LDS, 16-byte loads (L % 4 == 0,
+                           // L <= ttm_grouped_row_stage_max_L())
+  kGroupedRowsDirect = 3,  // B == 1, direct 16-byte row loads (L % 4 == 0)
   kGroupedRowsScalar = 4   // B == 1 through LDS, one element per load
+                           // (L <= ttm_grouped_row_stage_max_L())
 };
 struct TtmNodeDesc {
   const void* in;
@@ -44,6 +46,8 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
                           int64_t B, TtmNodeDesc* d, int64_t* tiles);
 // Dynamic LDS of the grouped kernel for nodes with L <= Lmax.
 size_t ttm_grouped_lds(int Lmax);
+// Longest rows the grouped kernel stages through LDS.
+int ttm_grouped_row_stage_max_L();
 // items: (node, tile) pairs, node an index into `nodes` (the whole table);
 // counter: zeroed device int (the queue head);
 // grid: persistent blocks.  Every node has K <= 16 and L <= Lmax; in_dtype

@@ -135,13 +135,17 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
 
 // ------------------------------------------------------------------- row path --
 // B == 1 (the last mode): Out[a, k] = sum_l In[a, l] F[l, k], rows of In
-// contiguous.  Requires L % 4 == 0.  Lane i owns row a = 256*block + thread and
-// walks it with 16-byte loads (eight in flight: one 128-byte line of FP32);
-// each load feeds four MFMAs, one per l.  In a 4x4x1 MFMA the B operand of
-// lane i is its own row value, the A operands (four k's of row l of F) are
-// the same for every block, so lane i accumulates four k's of its own row.
+// contiguous.  In a 4x4x1 MFMA the B operand of lane i is a value of its own
+// row a, the A operands (four k's of row l of F) are the same for every block,
+// so lane i accumulates four k's of row a.
+//
+// Direct variant, for rows too long to stage the factor slice beside the row
+// tiles below: requires L % 4 == 0.  Lane i owns row a = 256*block + thread
+// and walks it with 16-byte loads (eight in flight); each load feeds four
+// MFMAs, one per l.  Every load instruction touches 64 rows, so it moves less
+// than the staged variant.
 template <int KG, typename TIn, bool NT>
-__device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const float* __restrict__ F,
+__device__ __forceinline__ void rows_direct_body(const TIn* __restrict__ in, const float* __restrict__ F,
                                           float* __restrict__ out, int64_t A, int L, int Kt,
                                           int64_t blk, int k0, float* smem) {
   stage_factor<KG>(smem, F, L, Kt, k0);
@@ -193,6 +197,104 @@ __device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const floa
 }
 
 template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_rows_direct_f32(const TIn* __restrict__ in,
+                                                           const float* __restrict__ F,
+                                                           float* __restrict__ out, int64_t A,
+                                                           int L, int Kt) {
+  extern __shared__ float smem[];
+  rows_direct_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+}
+
+// Staged variants: a wave owns 64 consecutive rows and reads them
+// cooperatively in chunks of kRowLC columns into a padded LDS tile of its own
+// (pitch kRowLC + 1, so the 64 lanes reading one column hit distinct banks);
+// then every lane runs the MFMA chain over its own row.
+constexpr int kRowLC = 32;
+constexpr int kRowPitch = kRowLC + 1;
+constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  // 4 waves
+
+// Orders this wave's LDS accesses for the compiler; the LDS itself executes
+// one wave's accesses in issue order, so no wait is needed between them.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 16-byte variant (L % 4 == 0, rows aligned for four-element loads): load
+// slot u of a lane covers four columns of row 8u + lane/8, so eight lanes read
+// 128 contiguous bytes of FP32 and every load instruction eight full segments.
+// The next chunk's loads are issued before the current chunk's MFMAs, and the
+// tile is private to the wave: after the factor is staged the waves of a
+// block never wait for each other.
+template <int KG, typename TIn, bool NT>
+__device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const float* __restrict__ F,
+                                          float* __restrict__ out, int64_t A, int L, int Kt,
+                                          int64_t blk, int k0, float* smem) {
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = blk * 256 + wave * 64;
+  if (row0 >= A) return;  // whole wave idle
+  const int nrows = (int)min((int64_t)64, A - row0);
+  float* Xs = smem + 4 * L * KG + wave * 64 * kRowPitch;
+  const float* ft = smem + (lane & 3) * L * KG;
+  const int rq = lane >> 3, cq = 4 * (lane & 7);
+  // slots past the wave's last row re-read that row
+  const TIn* rp[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) rp[u] = in + (row0 + min(8 * u + rq, nrows - 1)) * (int64_t)L;
+
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+
+  f4 v[8];
+  // in a short last chunk, lanes past its end re-read its last four columns
+  auto load_chunk = [&](int l0) {
+    const int c = l0 + min(cq, min(kRowLC, L - l0) - 4);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = load4_f32<NT>(rp[u] + c);
+  };
+  load_chunk(0);
+  const float* xr = Xs + lane * kRowPitch;
+  for (int l0 = 0; l0 < L; l0 += kRowLC) {
+    wave_lds_fence();  // the previous chunk's reads are issued before these writes
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Xs[(8 * u + rq) * kRowPitch + cq + j] = v[u][j];
+    wave_lds_fence();
+    if (l0 + kRowLC < L) load_chunk(l0 + kRowLC);
+    if (L - l0 >= kRowLC) {
+#pragma unroll
+      for (int c = 0; c < kRowLC; ++c)
+#pragma unroll
+        for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + c) * KG + g], xr[c], acc[g]);
+    } else {
+      for (int c = 0; c < L - l0; ++c)
+#pragma unroll
+        for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[(l0 + c) * KG + g], xr[c], acc[g]);
+    }
+  }
+  if (lane >= nrows) return;
+  float* q = out + (row0 + lane) * Kt;
+  if (Kt % 4 == 0 && (uintptr_t)out % 16 == 0) {
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+      if (k0 + 4 * g < Kt) *reinterpret_cast<f4*>(q + k0 + 4 * g) = acc[g];
+  } else {
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = k0 + 4 * g + m;
+        if (k < Kt) q[k] = acc[g][m];
+      }
+  }
+}
+
+template <int KG, typename TIn, bool NT>
 __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
                                                     const float* __restrict__ F,
                                                     float* __restrict__ out, int64_t A, int L,
@@ -201,21 +303,11 @@ __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
   rows_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
-// Row path through LDS (B == 1): the rows of a wave (64 consecutive a, each a
-// contiguous run of L values) are loaded cooperatively in chunks of
-// kRowLC columns -- eight lanes cover 128 contiguous bytes of one row, so
-// every load instruction reads eight full 128-byte segments -- into a padded
-// LDS tile (pitch kRowLC + 1: conflict-free column reads), then every lane
-// runs the MFMA chain over its own row.  V4: 16-byte loads (L % 4 == 0 and a
-// base aligned for them); otherwise one element per load, 32 in flight.
-constexpr int kRowLC = 32;
-constexpr int kRowPitch = kRowLC + 1;
-constexpr size_t kRowStageBytes = (size_t)4 * 64 * kRowPitch * sizeof(float);  // 4 waves
-// Rows up to this length go through LDS; longer rows are read directly (a
-// lane's eight 16-byte loads then cover 128 contiguous bytes of its row).
-constexpr int kRowLdsMaxL = 64;
-
-template <int KG, typename TIn, bool NT, bool V4>
+// Single-element variant, for rows that cannot be read 16 bytes at a time
+// (odd L, or an unaligned base): one element per load, 32 in flight, eight
+// rows' 32 consecutive elements per load instruction; block barriers around
+// each chunk.
+template <int KG, typename TIn, bool NT>
 __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
                                               const float* __restrict__ F,
                                               float* __restrict__ out, int64_t A, int L, int Kt,
@@ -236,37 +328,18 @@ __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
   for (int l0 = 0; l0 < L; l0 += kRowLC) {
     const int lc = min(kRowLC, L - l0);
     __syncthreads();  // the previous chunk has been consumed (and FT staged)
-    if constexpr (V4) {
-      constexpr int kPer = 64 * kRowLC / 4 / 64;  // 16-byte loads per lane
-      f4 v[kPer];
+    constexpr int kPer = 64 * kRowLC / 64;  // one element per load
+    float v[kPer];
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int q = lane + 64 * u;
-        const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
-        v[u] = (r < nrows && c < lc) ? load4_f32<NT>(in + (row0 + r) * L + l0 + c)
-                                     : f4{0.f, 0.f, 0.f, 0.f};
-      }
+    for (int u = 0; u < kPer; ++u) {
+      const int q = lane + 64 * u;
+      const int r = q / kRowLC, c = q % kRowLC;
+      v[u] = (r < nrows && c < lc) ? Elem<TIn>::to_f32(in[(row0 + r) * L + l0 + c]) : 0.f;
+    }
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int q = lane + 64 * u;
-        const int r = q / (kRowLC / 4), c = 4 * (q % (kRowLC / 4));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Xs[r * kRowPitch + c + j] = v[u][j];
-      }
-    } else {
-      constexpr int kPer = 64 * kRowLC / 64;  // one element per load
-      float v[kPer];
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int q = lane + 64 * u;
-        const int r = q / kRowLC, c = q % kRowLC;
-        v[u] = (r < nrows && c < lc) ? Elem<TIn>::to_f32(in[(row0 + r) * L + l0 + c]) : 0.f;
-      }
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int q = lane + 64 * u;
-        Xs[(q / kRowLC) * kRowPitch + q % kRowLC] = v[u];
-      }
+    for (int u = 0; u < kPer; ++u) {
+      const int q = lane + 64 * u;
+      Xs[(q / kRowLC) * kRowPitch + q % kRowLC] = v[u];
     }
     __syncthreads();
     for (int c = 0; c < lc; ++c) {
@@ -286,13 +359,13 @@ __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
     }
 }
 
-template <int KG, typename TIn, bool NT, bool V4>
+template <int KG, typename TIn, bool NT>
 __global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
                                                         const float* __restrict__ F,
                                                         float* __restrict__ out, int64_t A, int L,
                                                         int Kt) {
   extern __shared__ float smem[];
-  rows_lds_body<KG, TIn, NT, V4>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+  rows_lds_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
 // ------------------------------------------------------------- BF16 MFMA paths --
@@ -653,11 +726,11 @@ __global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict
     if (d.path == kGroupedWide)
       wide_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0, smem);
     else if (d.path == kGroupedRows)
-      rows_lds_body<4, TIn, NT, true>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
-    else if (d.path == kGroupedRowsScalar)
-      rows_lds_body<4, TIn, NT, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
-    else if (d.path == kGroupedRowsDirect)
       rows_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedRowsScalar)
+      rows_lds_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedRowsDirect)
+      rows_direct_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
     else
       tile_body<4, TIn>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.B, d.K, d.na, d.nb, d.nbt, w.y,
                         0, smem);
@@ -782,6 +855,13 @@ int pick_kg(int64_t K, int kg_cap, int64_t blocks) {
   return kg;
 }
 
+// Rows that the 16-byte row body can read: L % 4 == 0, base aligned for
+// four-element loads.
+template <typename TIn>
+bool rows_v4(const TIn* in, int64_t L) {
+  return L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
+}
+
 template <typename TIn, int KG, bool NT>
 hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
                          int K, float* out, hipStream_t st) {
@@ -794,21 +874,23 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
                        K);
   } else if (path == Path::kRows) {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
-    const bool v4 = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
-    if (!v4 || L <= kRowLdsMaxL) {
-      // short rows (a lane's 16-byte loads would touch one cache segment each)
-      // or rows that cannot be read 16 bytes at a time: staged through LDS
-      const size_t lds = (size_t)16 * L * KG + kRowStageBytes;
-      if (v4)
-        hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT, true>), grid, dim3(256), lds, st, in,
-                           F, out, A, L, K);
+    const size_t staged = (size_t)16 * L * KG + kRowStageBytes;
+    if (!rows_v4(in, L)) {
+      hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT>), grid, dim3(256), staged, st, in, F,
+                         out, A, L, K);
+    } else if (staged <= (size_t)kLdsBudget) {
+      // rows that are not whole 128-byte lines share a line with the next
+      // column chunk: normal loads keep it cached until then
+      if (NT && (L * sizeof(TIn)) % 128 == 0)
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, true>), grid, dim3(256), staged, st, in, F,
+                           out, A, L, K);
       else
-        hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT, false>), grid, dim3(256), lds, st, in,
-                           F, out, A, L, K);
-    } else {
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, false>), grid, dim3(256), staged, st, in, F,
+                           out, A, L, K);
+    } else {  // the factor slice leaves no room for the row tiles
       const size_t lds = (size_t)16 * L * KG;
-      hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, A,
-                         L, K);
+      hipLaunchKernelGGL((ttm_rows_direct_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F,
+                         out, A, L, K);
     }
   } else {
     const int nb = (int)std::min<int64_t>(B, 256);
@@ -853,15 +935,14 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
                       float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
   Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
-  // LDS beside the factor slice: the staged tile, or the row stage for short rows
-  const bool rows_v4 = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
-  // rows staged through LDS need the stage beside one K-group at least
-  if (path == Path::kRows && (L <= kRowLdsMaxL || !rows_v4) &&
-      (size_t)16 * L + kRowStageBytes > (size_t)kLdsBudget)
-    path = Path::kTile;
-  const int stage = (path == Path::kRows && (L <= kRowLdsMaxL || !rows_v4)) ? (int)kRowStageBytes
-                    : path == Path::kTile                      ? 4 * kTileLC * 256
-                                                               : 0;
+  // LDS beside the factor slice: the staged tile, or the row tiles when one
+  // K-group fits beside them (else 16-byte rows are read directly, and
+  // single-element rows take the tile path)
+  const bool row_stage = (size_t)16 * L + kRowStageBytes <= (size_t)kLdsBudget;
+  if (path == Path::kRows && !rows_v4(in, L) && !row_stage) path = Path::kTile;
+  const int stage = (path == Path::kRows && row_stage) ? (int)kRowStageBytes
+                    : path == Path::kTile              ? 4 * kTileLC * 256
+                                                       : 0;
   int kg = pick_kg(K, std::max(1, (kLdsBudget - std::max(stage, 4 * kTileLC * 256)) / (16 * L)),
                    grid_blocks(path, A, B));
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
@@ -973,8 +1054,9 @@ hipError_t launch_f64_kc(const double* in, int64_t A, int L, int64_t B, const do
 }  // namespace
 
 // Longest rows the grouped kernel stages through LDS (factor slice of four
-// K-groups plus the row stage within the LDS budget).
+// K-groups plus the row tiles within the LDS budget).
 constexpr int kGroupedRowStageMaxL = (int)((kLdsBudget - kRowStageBytes) / (16 * 4));
+int ttm_grouped_row_stage_max_L() { return kGroupedRowStageMaxL; }
 
 void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_t A, int64_t L,
                           int64_t B, TtmNodeDesc* d, int64_t* tiles) {
@@ -987,10 +1069,10 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
     *tiles = (A * B + 1023) / 1024;
   } else if (B == 1 && ((L % 4 == 0 && in_al) || L <= kGroupedRowStageMaxL)) {
     // 256 rows per item: through LDS (16-byte or single loads) or direct
-    if (L % 4 == 0 && in_al)
-      d->path = L <= kRowLdsMaxL ? kGroupedRows : kGroupedRowsDirect;
+    if (L > kGroupedRowStageMaxL)
+      d->path = kGroupedRowsDirect;
     else
-      d->path = kGroupedRowsScalar;
+      d->path = L % 4 == 0 && in_al ? kGroupedRows : kGroupedRowsScalar;
     *tiles = (A + 255) / 256;
   } else {
     d->path = kGroupedTile;

@@ -33,6 +33,11 @@ TTM_CASES = [
     (1000, 64, 1, 20),   # row path (B = 1, L % 4 == 0)
     (257, 200, 1, 37),   # row path, K over several groups, ragged rows
     (5, 48, 1, 3),       # row path, tiny grid
+    (300, 68, 1, 12),    # row tiles: short last column chunk, last wave partial
+    (70, 4, 1, 5),       # row tiles: one four-column chunk
+    (1, 36, 1, 2),       # row tiles: a single row
+    (2000, 1000, 1, 8),  # row tiles: one K-group beside the tiles, two K-chunks
+    (300, 2000, 1, 4),   # rows too long for the tiles: direct row loads
 ]
 
 
@@ -50,7 +55,7 @@ def test_ttm_fp32(A, L, B, K):
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-3:])
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-8:])
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
@@ -138,7 +143,13 @@ def test_ttm_identity_factor_copies_input():
 
 @pytest.mark.parametrize("A,L,B,dtype", [(1, 200, 8000, "f32"), (400, 200, 20, "f32"),
                                          (8000, 200, 1, "f32"), (3, 70, 13, "f64"),
-                                         (16, 130, 16, "f32"), (5, 64, 33, "bf16")])
+                                         (16, 130, 16, "f32"), (5, 64, 33, "bf16"),
+                                         # few rows over many columns; one row; one
+                                         # valid row in the last 64-row tile with a
+                                         # ragged last column chunk; B = 1 from BF16
+                                         (200, 20, 400, "f32"), (2, 1, 50, "f32"),
+                                         (1, 65, 12345, "f32"), (7, 17, 1, "bf16"),
+                                         (300, 33, 1, "f64")])
 def test_gram(A, L, B, dtype):
     torch, dev = torch_dev()
     print(f"gram A={A} L={L} B={B} {dtype}", flush=True)
