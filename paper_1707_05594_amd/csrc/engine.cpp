@@ -69,6 +69,9 @@ struct tk_ctx {
   // BF16 (those consumers round their input to BF16 anyway); everything else,
   // leaf tensors included, is stored in wdtype.
   std::vector<int> node_out_dt;
+  // per tree node: its input is read once (T, or a parent with no other
+  // child), so the TTM streams it with non-temporal loads
+  std::vector<char> node_stream;
   int in_dtype_of(int u) const {
     const int p = tree.nodes[u].parent;
     return p < 0 ? tdtype : node_out_dt[p];
@@ -312,9 +315,8 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
     view(s, nd.pre_mask, nd.mode, &A, &L, &B);
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
     if (!nd.is_leaf) {
-      // children of the root stream T (too large to stay in cache between them)
       TK_HIP(launch_ttm(in_dt, c->node_compute[u], in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
-                        c->wsp(c->node_off[u]), c->st, nd.parent < 0, c->node_tile[u],
+                        c->wsp(c->node_off[u]), c->st, c->node_stream[u], c->node_tile[u],
                         c->node_out_dt[u]));
     } else {
       const int n = nd.mode;
@@ -363,7 +365,8 @@ int core_chain(tk_ctx* c, int dst) {
     int64_t A, L, B;
     view(s, pre, n, &A, &L, &B);
     void* out = (i == N - 1) ? c->core : c->wsp((i % 2 == 0) ? 0 : c->chain_a);
-    TK_HIP(launch_ttm(in_dt, c->core_compute, in, A, L, B, c->fc(n), s.K[n], out, c->st, i == 0));
+    // every input of the chain is read once
+    TK_HIP(launch_ttm(in_dt, c->core_compute, in, A, L, B, c->fc(n), s.K[n], out, c->st, true));
     pre |= 1u << n;
     in = out;
     in_dt = c->wdtype;
@@ -570,8 +573,17 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   // depends on its input's type).  A node whose output is a leaf tensor keeps
   // it in wdtype: the Gram reads the leaf unrounded.
   std::vector<char> feeds_leaf(nodes.size(), 0);
+  std::vector<int> children(nodes.size(), 0);
   for (const tk_node& nd : nodes)
-    if (nd.is_leaf && nd.parent >= 0) feeds_leaf[nd.parent] = 1;
+    if (nd.parent >= 0) {
+      children[nd.parent]++;
+      if (nd.is_leaf) feeds_leaf[nd.parent] = 1;
+    }
+  // T is streamed by every child of the root (too large to stay in cache
+  // between them); an intermediate with one consumer is read once
+  c->node_stream.assign(nodes.size(), 0);
+  for (size_t u = 0; u < nodes.size(); ++u)
+    c->node_stream[u] = nodes[u].parent < 0 || children[nodes[u].parent] == 1;
   c->node_out_dt.assign(nodes.size(), -1);
   for (size_t u0 = 0; u0 < nodes.size(); ++u0) {
     std::vector<int> up;
