@@ -6,10 +6,10 @@
 //     S[i, j] = sum_{a, b} Y[a, i, b] * Y[a, j, b].
 // The columns are cut into fixed chunks; every block computes one 64 x 64
 // tile (i-tile <= j-tile, symmetry) of one chunk's partial Gram with FP64
-// FMAs on LDS-staged rows (FP32/BF16 inputs convert exactly to FP64, so the
+// MFMAs on LDS-staged rows (FP32/BF16 inputs convert exactly to FP64, so the
 // products are exact and only the FP64 sums round).  A second kernel adds the
-// chunk partials in fixed chunk order and mirrors the tile: the result is
-// bitwise deterministic for a given shape.
+// chunk partials in a fixed order and mirrors the tile: the result is bitwise
+// deterministic for a given shape.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,8 +20,11 @@
 
 namespace tk {
 
-constexpr int kGT = 64;  // tile rows
-constexpr int kGC = 32;  // columns per LDS step
+constexpr int kGT = 64;       // tile rows
+constexpr int kGC = 32;       // columns per LDS step
+constexpr int kGP = kGT + 1;  // LDS pitch (doubles): column-fastest stores spread over banks
+
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void pair_of(int p, int T, int* ti, int* tj) {
   int i = 0;
@@ -33,102 +36,114 @@ __device__ __forceinline__ void pair_of(int p, int T, int* ti, int* tj) {
   *tj = i + p;
 }
 
+// One kGC-column step of a 64-row tile: 8 elements per thread, converted to
+// FP64 (exact); zeros past the chunk's end and past row L.  B == 1: Y[a, l],
+// a column's rows are contiguous and threads walk rows fastest; otherwise
+// consecutive columns (b) are contiguous and threads walk columns fastest, so
+// a thread keeps one column c = (a, b) for the whole step.
 template <typename TIn>
-__device__ __forceinline__ void gram_load_tile(double (*X)[kGT], const TIn* __restrict__ Y,
-                                               int L, int64_t B, int row0, int64_t cs,
-                                               int64_t cend) {
-  // kGC * kGT / 256 = 8 elements per thread, all loads issued before the stores
+__device__ __forceinline__ void gram_load_step(double (&v)[8], const TIn* __restrict__ Y, int L,
+                                               int64_t B, int row0, int64_t cs, int64_t cend) {
   const int tid = threadIdx.x;
-  constexpr int kPer = kGC * kGT / 256;
-  double v[kPer];
   if (B == 1) {
-    // Y[a, l]: rows of one column are contiguous -> threads walk rows fastest
+    const int row = row0 + tid % kGT;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + 256 * u;
-      const int rr = e % kGT, cc = e / kGT;
-      const int64_t c = cs + cc;
-      const int row = row0 + rr;
+    for (int u = 0; u < 8; ++u) {
+      const int64_t c = cs + tid / kGT + 4 * u;
       v[u] = (c < cend && row < L) ? Elem<TIn>::to_f64(Y[c * L + row]) : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + 256 * u;
-      X[e / kGT][e % kGT] = v[u];
-    }
   } else {
+    const int64_t c = cs + tid % kGC;
+    const int64_t a = c / B;
+    const TIn* base = Y + a * L * B + (c - a * B);
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + 256 * u;
-      const int cc = e % kGC, rr = e / kGC;
-      const int64_t c = cs + cc;
-      const int row = row0 + rr;
-      double x = 0.0;
-      if (c < cend && row < L) {
-        const int64_t a = c / B;
-        const int64_t b = c - a * B;
-        x = Elem<TIn>::to_f64(Y[(a * L + row) * B + b]);
-      }
-      v[u] = x;
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int e = tid + 256 * u;
-      X[e % kGC][e / kGC] = v[u];
+    for (int u = 0; u < 8; ++u) {
+      const int row = row0 + tid / kGC + 8 * u;
+      v[u] = (c < cend && row < L) ? Elem<TIn>::to_f64(base[(int64_t)row * B]) : 0.0;
     }
   }
 }
+__device__ __forceinline__ void gram_store_step(double (*X)[kGP], const double (&v)[8], bool b1) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (b1)
+      X[tid / kGT + 4 * u][tid % kGT] = v[u];
+    else
+      X[tid % kGC][tid / kGC + 8 * u] = v[u];
+  }
+}
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // Partial Gram of column chunk `chunk` for tile pair `pair` -> one 64 x 64
-// block of `part`.
+// block of `part` (row index in tile ti, column index in tile tj).  Wave w
+// owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of
+// v_mfma_f64_16x16x4_f64: per four columns, lane l supplies row l % 16 of
+// column l / 16 for both operands (A = the ti rows, B = the tj rows), and
+// holds D[l / 16 + 4 r][l % 16] in register r.  16-row blocks entirely past
+// row L are skipped.  The next step's elements are loaded while the current
+// one is multiplied.
 template <typename TIn>
 __device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int L, int64_t B,
                                                   int64_t C, int64_t cchunk, int T, int npairs,
                                                   double* __restrict__ part, int chunk, int pair,
-                                                  double (*Xi)[kGT], double (*Xj)[kGT]) {
+                                                  double (*Xi)[kGP], double (*Xj)[kGP]) {
   int ti, tj;
   pair_of(pair, T, &ti, &tj);
   const int64_t cbeg = (int64_t)chunk * cchunk;
   const int64_t cend = min(C, cbeg + cchunk);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc[r][s] = 0.0;
   const bool diag = (ti == tj);
+  const bool b1 = B == 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rq = (wave >> 1) * 32, cq = (wave & 1) * 32;
+  const bool vi0 = ti * kGT + rq < L, vi1 = ti * kGT + rq + 16 < L;
+  const bool vj0 = tj * kGT + cq < L, vj1 = tj * kGT + cq + 16 < L;
+  d4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  double (*Xb)[kGP] = diag ? Xi : Xj;
+
+  double vi[8], vj[8];
+  gram_load_step<TIn>(vi, Y, L, B, ti * kGT, cbeg, cend);
+  if (!diag) gram_load_step<TIn>(vj, Y, L, B, tj * kGT, cbeg, cend);
+  const int r = lane & 15, k4 = lane >> 4;
   for (int64_t cs = cbeg; cs < cend; cs += kGC) {
+    __syncthreads();  // the previous step has been multiplied
+    gram_store_step(Xi, vi, b1);
+    if (!diag) gram_store_step(Xj, vj, b1);
     __syncthreads();
-    gram_load_tile<TIn>(Xi, Y, L, B, ti * kGT, cs, cend);
-    if (!diag) gram_load_tile<TIn>(Xj, Y, L, B, tj * kGT, cs, cend);
-    __syncthreads();
-    double (*Xb)[kGT] = diag ? Xi : Xj;
-#pragma unroll 4
-    for (int cc = 0; cc < kGC; ++cc) {
-      double ai[4], bj[4];
+    if (cs + kGC < cend) {
+      gram_load_step<TIn>(vi, Y, L, B, ti * kGT, cs + kGC, cend);
+      if (!diag) gram_load_step<TIn>(vj, Y, L, B, tj * kGT, cs + kGC, cend);
+    }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) ai[r] = Xi[cc][4 * ty + r];
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bj[s] = Xb[cc][4 * tx + s];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc[r][s] = fma(ai[r], bj[s], acc[r][s]);
+    for (int k = 0; k < kGC; k += 4) {
+      const double a0 = Xi[k + k4][rq + r], a1 = Xi[k + k4][rq + 16 + r];
+      const double b0 = Xb[k + k4][cq + r], b1v = Xb[k + k4][cq + 16 + r];
+      if (vi0 && vj0) acc00 = mfma_f64(a0, b0, acc00);
+      if (vi0 && vj1) acc01 = mfma_f64(a0, b1v, acc01);
+      if (vi1 && vj0) acc10 = mfma_f64(a1, b0, acc10);
+      if (vi1 && vj1) acc11 = mfma_f64(a1, b1v, acc11);
     }
   }
   double* out = part + ((int64_t)chunk * npairs + pair) * (kGT * kGT);
+  const int i0 = rq + k4, j0 = cq + r;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) out[(4 * ty + r) * kGT + 4 * tx + s] = acc[r][s];
+  for (int q = 0; q < 4; ++q) {
+    out[(i0 + 4 * q) * kGT + j0] = acc00[q];
+    out[(i0 + 4 * q) * kGT + j0 + 16] = acc01[q];
+    out[(i0 + 16 + 4 * q) * kGT + j0] = acc10[q];
+    out[(i0 + 16 + 4 * q) * kGT + j0 + 16] = acc11[q];
+  }
 }
 
 template <typename TIn>
 __global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, int L, int64_t B,
                                                     int64_t C, int64_t cchunk, int T,
                                                     int npairs, double* __restrict__ part) {
-  __shared__ double Xi[kGC][kGT];
-  __shared__ double Xj[kGC][kGT];
+  __shared__ double Xi[kGC][kGP];
+  __shared__ double Xj[kGC][kGP];
   gram_partial_body<TIn>(Y, L, B, C, cchunk, T, npairs, part, blockIdx.x, blockIdx.y, Xi, Xj);
 }
 
@@ -136,19 +151,21 @@ __global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, i
 template <typename TIn>
 __global__ __launch_bounds__(256) void gram_grouped_partial(const GramDesc* __restrict__ mats,
                                                             const int4* __restrict__ items) {
-  __shared__ double Xi[kGC][kGT];
-  __shared__ double Xj[kGC][kGT];
+  __shared__ double Xi[kGC][kGP];
+  __shared__ double Xj[kGC][kGP];
   const int4 w = items[blockIdx.x];
   const GramDesc d = mats[w.x];
   gram_partial_body<TIn>((const TIn*)d.Y, d.L, d.B, d.C, d.cchunk, d.T, d.npairs, d.part, w.y,
                          w.z, Xi, Xj);
 }
 
-__global__ void gram_reduce(const double* __restrict__ part, int L, int T, int npairs,
-                            int nchunks, double* __restrict__ S) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)L * L) return;
-  int i = (int)(e / L), j = (int)(e % L);
+// Sum over chunks of element (i, j) of an L x L Gram: kRG thread groups of
+// kRE elements; group g adds chunks g, g + kRG, ... in order, then the group
+// sums are added in group order (a fixed order for a given shape).
+constexpr int kRG = 8, kRE = 32;
+
+__device__ __forceinline__ double gram_chunk_sum(const double* __restrict__ part, int L, int T,
+                                                 int npairs, int nchunks, int i, int j, int g) {
   int ii = i, jj = j;
   if (ii / kGT > jj / kGT) {
     ii = j;
@@ -156,43 +173,65 @@ __global__ void gram_reduce(const double* __restrict__ part, int L, int T, int n
   }
   const int ti = ii / kGT, tj = jj / kGT;
   const int p = ti * T - ti * (ti - 1) / 2 + (tj - ti);
-  const int li = ii - ti * kGT, lj = jj - tj * kGT;
+  const int64_t off = (int64_t)p * (kGT * kGT) + (ii - ti * kGT) * kGT + (jj - tj * kGT);
+  const int64_t stride = (int64_t)npairs * (kGT * kGT);
   double s = 0.0;
-  for (int ch = 0; ch < nchunks; ++ch)
-    s += part[((int64_t)ch * npairs + p) * (kGT * kGT) + li * kGT + lj];
-  S[e] = s;
+  for (int ch = g; ch < nchunks; ch += kRG) s += part[ch * stride + off];
+  return s;
+}
+
+__device__ __forceinline__ double combine_groups(double s, double (*red)[kRE]) {
+  const int g = threadIdx.x / kRE, q = threadIdx.x % kRE;
+  red[g][q] = s;
+  __syncthreads();
+  double t = 0.0;
+  if (g == 0)
+#pragma unroll
+    for (int h = 0; h < kRG; ++h) t += red[h][q];
+  return t;
+}
+
+__global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ part, int L, int T,
+                                                   int npairs, int nchunks,
+                                                   double* __restrict__ S) {
+  __shared__ double red[kRG][kRE];
+  const int g = threadIdx.x / kRE, q = threadIdx.x % kRE;
+  const int64_t e = (int64_t)blockIdx.x * kRE + q;
+  const bool ok = e < (int64_t)L * L;
+  const double s = ok ? gram_chunk_sum(part, L, T, npairs, nchunks, (int)(e / L), (int)(e % L), g)
+                      : 0.0;
+  const double t = combine_groups(s, red);
+  if (g == 0 && ok) S[e] = t;
 }
 
 // Element e of the concatenated L_m x L_m results of all matrices: matrix m
 // with elem_off[m] <= e < elem_off[m + 1] (binary search), then as gram_reduce.
-__global__ void gram_grouped_reduce(const GramDesc* __restrict__ mats,
-                                    const int64_t* __restrict__ elem_off, int n_mats) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= elem_off[n_mats]) return;
-  int lo = 0, hi = n_mats - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (elem_off[mid] <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const GramDesc d = mats[lo];
-  const int64_t r = e - elem_off[lo];
-  const int L = d.L;
-  const int i = (int)(r / L), j = (int)(r % L);
-  int ii = i, jj = j;
-  if (ii / kGT > jj / kGT) {
-    ii = j;
-    jj = i;
-  }
-  const int ti = ii / kGT, tj = jj / kGT;
-  const int p = ti * d.T - ti * (ti - 1) / 2 + (tj - ti);
-  const int li = ii - ti * kGT, lj = jj - tj * kGT;
+__global__ __launch_bounds__(256) void gram_grouped_reduce(const GramDesc* __restrict__ mats,
+                                                           const int64_t* __restrict__ elem_off,
+                                                           int n_mats) {
+  __shared__ double red[kRG][kRE];
+  const int g = threadIdx.x / kRE, q = threadIdx.x % kRE;
+  const int64_t e = (int64_t)blockIdx.x * kRE + q;
+  const bool ok = e < elem_off[n_mats];
   double s = 0.0;
-  for (int ch = 0; ch < d.nchunks; ++ch)
-    s += d.part[((int64_t)ch * d.npairs + p) * (kGT * kGT) + li * kGT + lj];
-  d.S[r] = s;
+  int lo = 0;
+  int64_t rel = 0;
+  if (ok) {
+    int hi = n_mats - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (elem_off[mid] <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const GramDesc d = mats[lo];
+    rel = e - elem_off[lo];
+    s = gram_chunk_sum(d.part, d.L, d.T, d.npairs, d.nchunks, (int)(rel / d.L),
+                       (int)(rel % d.L), g);
+  }
+  const double t = combine_groups(s, red);
+  if (g == 0 && ok) mats[lo].S[rel] = t;
 }
 
 namespace {
@@ -244,8 +283,8 @@ hipError_t launch_gram_grouped(int in_dtype, const GramDesc* mats, const int4* i
                        items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_grouped_reduce, dim3((unsigned)((total_elems + 255) / 256)), dim3(256),
-                     0, st, mats, elem_off, n_mats);
+  hipLaunchKernelGGL(gram_grouped_reduce, dim3((unsigned)((total_elems + kRE - 1) / kRE)),
+                     dim3(256), 0, st, mats, elem_off, n_mats);
   return hipGetLastError();
 }
 
@@ -272,7 +311,7 @@ hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = L * L;
-  hipLaunchKernelGGL(gram_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
+  hipLaunchKernelGGL(gram_reduce, dim3((unsigned)((n + kRE - 1) / kRE)), dim3(256), 0, st, part,
                      (int)L, g.T, g.npairs, (int)g.nchunks, S);
   return hipGetLastError();
 }
