@@ -58,6 +58,59 @@ __device__ __forceinline__ void stage_factor(float* FT, const float* __restrict_
 // columns c0 + 4i .. c0 + 4i + 3 (same a, consecutive b).  grid.y splits K
 // into chunks of 4*KG rows.  NT: the input is streamed (read once, e.g. T at
 // the root), so its loads bypass cache retention.
+// MFMA chain of one wide-path lane over rows [l0, l1) of its four columns
+// (input at p, row stride B); acc[g][j][m] is output k = k0 + 4g + m of
+// column j.
+template <int KG, typename TIn, bool NT>
+__device__ __forceinline__ void wide_chain(const TIn* __restrict__ p, int64_t B,
+                                           const float* __restrict__ ft, int l0, int l1,
+                                           f4 (&acc)[KG][4]) {
+  constexpr int U = 8;
+  int l = l0;
+  for (; l + U <= l1; l += U) {
+    f4 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      x[u] = load4_f32<NT>(p + (int64_t)(l + u) * B);
+    // keep the batch of loads together ahead of the MFMAs that consume them
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        const float fa = ft[(l + u) * KG + g];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+      }
+    }
+  }
+  for (; l < l1; ++l) {
+    const f4 x = load4_f32<NT>(p + (int64_t)l * B);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const float fa = ft[l * KG + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[j], acc[g][j]);
+    }
+  }
+}
+
+template <int KG>
+__device__ __forceinline__ void wide_store(float* __restrict__ out, int64_t a, int64_t b,
+                                           int64_t B, int Kt, int k0, const f4 (&acc)[KG][4]) {
+  float* q = out + (a * Kt) * B + b;
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt) {
+        f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
+        *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
+      }
+    }
+}
+
 template <int KG, typename TIn, bool NT>
 __device__ __forceinline__ void wide_body(const TIn* __restrict__ in, const float* __restrict__ F,
                                           float* __restrict__ out, int64_t C, int L, int64_t B,
@@ -81,47 +134,85 @@ __device__ __forceinline__ void wide_body(const TIn* __restrict__ in, const floa
   for (int g = 0; g < KG; ++g)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  wide_chain<KG, TIn, NT>(p, B, ft, 0, L, acc);
+  if (active) wide_store<KG>(out, a, b, B, Kt, k0, acc);
+}
 
-  constexpr int U = 8;
-  int l = 0;
-  for (; l + U <= L; l += U) {
-    f4 x[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      x[u] = load4_f32<NT>(p + (int64_t)(l + u) * B);
-    // keep the batch of loads together ahead of the MFMAs that consume them
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int g = 0; g < KG; ++g) {
-        const float fa = ft[(l + u) * KG + g];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
-      }
-    }
-  }
-  for (; l < L; ++l) {
-    const f4 x = load4_f32<NT>(p + (int64_t)l * B);
-#pragma unroll
-    for (int g = 0; g < KG; ++g) {
-      const float fa = ft[l * KG + g];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[j], acc[g][j]);
-    }
-  }
-  if (!active) return;
-  float* q = out + (a * Kt) * B + b;
+// Split-L variant for grids too small to fill the chip: the four waves of a
+// block share 256 columns and take four contiguous ranges of rows l (whole
+// batches of eight); waves 1..3 leave their partial sums in LDS, over the
+// factor slice once every wave is done with it, and wave 0 adds them in wave
+// order (a fixed order) and stores.  The input is still read once.
+constexpr int kSplitLMaxKG = 5;  // 3 partial sets of 16 KG floats per lane fit in 64 KB
+constexpr size_t splitl_lds(int L, int KG) {
+  return std::max((size_t)16 * L * KG, (size_t)3 * 16 * KG * 64 * sizeof(float));
+}
+
+template <int KG, typename TIn, bool NT>
+__device__ __forceinline__ void wide_splitl_body(const TIn* __restrict__ in,
+                                                 const float* __restrict__ F,
+                                                 float* __restrict__ out, int64_t C, int L,
+                                                 int64_t B, int Kt, int64_t blk, int k0,
+                                                 float* smem) {
+  static_assert(KG <= kSplitLMaxKG, "partials exceed the LDS budget");
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c = blk * 256 + 4 * lane;
+  const bool active = c < C;
+  const int64_t a = active ? c / B : 0;
+  const int64_t b = active ? c - a * B : 0;
+  const TIn* p = in + (a * L) * B + b;
+  const float* ft = smem + (lane & 3) * L * KG;
+  const int lq = ((L + 3) / 4 + 7) / 8 * 8;
+  const int l0 = min(L, wave * lq), l1 = min(L, l0 + lq);
+
+  f4 acc[KG][4];
 #pragma unroll
   for (int g = 0; g < KG; ++g)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int k = k0 + 4 * g + m;
-      if (k < Kt) {
-        f4 v = {acc[g][0][m], acc[g][1][m], acc[g][2][m], acc[g][3][m]};
-        *reinterpret_cast<f4*>(q + (int64_t)k * B) = v;
-      }
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  wide_chain<KG, TIn, NT>(p, B, ft, l0, l1, acc);
+  __syncthreads();  // every wave is done with the factor slice
+  // partial set w - 1, element e = (g, j, m): red[((w - 1) * 16 KG + e) * 64 + lane]
+  if (wave > 0) {
+    float* red = smem + (wave - 1) * 16 * KG * 64 + lane;
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) red[((g * 4 + j) * 4 + m) * 64] = acc[g][j][m];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  // one K-group at a time, partial sets in wave order (few live registers)
+#pragma unroll
+  for (int g = 0; g < KG; ++g) {
+    const float* red = smem + g * 16 * 64 + lane;
+#pragma unroll 1
+    for (int w = 0; w < 3; ++w) {
+      float v[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = red[(w * 16 * KG + e) * 64];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) acc[g][j][m] += v[j * 4 + m];
     }
+  }
+  if (active) wide_store<KG>(out, a, b, B, Kt, k0, acc);
+}
+
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_wide_splitl_f32(const TIn* __restrict__ in,
+                                                           const float* __restrict__ F,
+                                                           float* __restrict__ out, int64_t C,
+                                                           int L, int64_t B, int Kt) {
+  extern __shared__ float smem[];
+  if constexpr (KG <= kSplitLMaxKG)
+    wide_splitl_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
 template <int KG, typename TIn, bool NT>
@@ -802,7 +893,7 @@ namespace {
 
 constexpr int kLdsBudget = 64 * 1024;
 
-enum class Path { kWide, kRows, kTile };
+enum class Path { kWide, kWideSplitL, kRows, kTile };
 
 template <typename TIn>
 Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
@@ -817,6 +908,7 @@ constexpr int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
 
 int64_t grid_blocks(Path path, int64_t A, int64_t B) {
   if (path == Path::kWide) return (A * B + 1023) / 1024;
+  if (path == Path::kWideSplitL) return (A * B + 255) / 256;
   if (path == Path::kRows) return (A + 255) / 256;
   return 0;
 }
@@ -872,6 +964,12 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
     dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
     hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, C, L, B,
                        K);
+  } else if (path == Path::kWideSplitL) {
+    if (KG > kSplitLMaxKG || splitl_lds(L, KG) > (size_t)kLdsBudget) return hipErrorInvalidValue;
+    const int64_t C = A * B;
+    dim3 grid((unsigned)((C + 255) / 256), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_wide_splitl_f32<KG, TIn, NT>), grid, dim3(256), splitl_lds(L, KG), st,
+                       in, F, out, C, L, B, K);
   } else if (path == Path::kRows) {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
     const size_t staged = (size_t)16 * L * KG + kRowStageBytes;
@@ -943,8 +1041,15 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
   const int stage = (path == Path::kRows && row_stage) ? (int)kRowStageBytes
                     : path == Path::kTile              ? 4 * kTileLC * 256
                                                        : 0;
-  int kg = pick_kg(K, std::max(1, (kLdsBudget - std::max(stage, 4 * kTileLC * 256)) / (16 * L)),
-                   grid_blocks(path, A, B));
+  int kg_cap = std::max(1, (kLdsBudget - std::max(stage, 4 * kTileLC * 256)) / (16 * L));
+  // a wide grid that leaves CUs idle splits L over the waves of a block
+  // (when at least one K-group of the factor slice fits beside the partials)
+  if (path == Path::kWide && tile == TK_TILE_AUTO && grid_blocks(path, A, B) < 256 &&
+      splitl_lds(L, 1) <= (size_t)kLdsBudget) {
+    path = Path::kWideSplitL;
+    kg_cap = std::max(1, std::min(kSplitLMaxKG, kLdsBudget / (16 * L)));
+  }
+  int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in)
     return launch_f32_nt<TIn, true>(path, kg, in, A, L, B, F, K, out, st);

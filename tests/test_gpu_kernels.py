@@ -38,6 +38,9 @@ TTM_CASES = [
     (1, 36, 1, 2),       # row tiles: a single row
     (2000, 1000, 1, 8),  # row tiles: one K-group beside the tiles, two K-chunks
     (300, 2000, 1, 4),   # rows too long for the tiles: direct row loads
+    (5, 1, 64, 3),       # small wide grid (split L): one row, three waves idle
+    (1, 300, 32, 24),    # small wide grid: K over six chunks
+    (200, 200, 400, 20), # small wide grid: 313 blocks of 256 columns
 ]
 
 
@@ -55,7 +58,7 @@ def test_ttm_fp32(A, L, B, K):
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-8:])
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-11:])
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
