@@ -962,8 +962,14 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
     const int64_t C = A * B;
     const size_t lds = (size_t)16 * L * KG;
     dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F, out, C, L, B,
-                       K);
+    // runs of B that are not whole 128-byte lines share their boundary lines
+    // with a neighbouring wave: normal loads keep those lines cached
+    if (NT && (B * sizeof(TIn)) % 128 == 0)
+      hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, true>), grid, dim3(256), lds, st, in, F, out, C,
+                         L, B, K);
+    else
+      hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, false>), grid, dim3(256), lds, st, in, F, out, C,
+                         L, B, K);
   } else if (path == Path::kWideSplitL) {
     if (KG > kSplitLMaxKG || splitl_lds(L, KG) > (size_t)kLdsBudget) return hipErrorInvalidValue;
     const int64_t C = A * B;
@@ -1129,6 +1135,9 @@ hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* 
   if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
   int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
+  // a run (B columns, or a row of L) that is not a whole number of 128-byte
+  // lines shares its boundary lines with a neighbouring wave: normal loads
+  if ((path == Path::kWide ? B : (int64_t)L) * (int64_t)sizeof(TIn) % 128 != 0) stream_in = false;
   if (stream_in) {
     if (x3) return launch_bf16_nt<TIn, true, true, false>(path, kg, in, A, L, B, F, K, out, st);
     if (out_bf16)
