@@ -36,41 +36,65 @@ __device__ __forceinline__ void pair_of(int p, int T, int* ti, int* tj) {
   *tj = i + p;
 }
 
-// One kGC-column step of a 64-row tile: 8 elements per thread, converted to
-// FP64 (exact); zeros past the chunk's end and past row L.  B == 1: Y[a, l],
+// One kGC-column step of a 64-row tile: 8 elements per thread in their
+// stored type (converted to FP64, exactly, when written to LDS); zeros past
+// the chunk's end and past row L.  B == 1: Y[a, l],
 // a column's rows are contiguous and threads walk rows fastest; otherwise
 // consecutive columns (b) are contiguous and threads walk columns fastest, so
-// a thread keeps one column c = (a, b) for the whole step.
+// a thread keeps one column c = (a, b) for the whole step: `col` points at
+// row 0 of it, advanced by the caller from step to step.
 template <typename TIn>
-__device__ __forceinline__ void gram_load_step(double (&v)[8], const TIn* __restrict__ Y, int L,
-                                               int64_t B, int row0, int64_t cs, int64_t cend) {
+__device__ __forceinline__ void gram_load_step(TIn (&v)[8], const TIn* __restrict__ Y, int L,
+                                               int64_t B, int row0, int64_t cs, int64_t cend,
+                                               const TIn* __restrict__ col) {
   const int tid = threadIdx.x;
   if (B == 1) {
     const int row = row0 + tid % kGT;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t c = cs + tid / kGT + 4 * u;
-      v[u] = (c < cend && row < L) ? Elem<TIn>::to_f64(Y[c * L + row]) : 0.0;
+      v[u] = (c < cend && row < L) ? Y[c * L + row] : TIn(0);
     }
   } else {
-    const int64_t c = cs + tid % kGC;
-    const int64_t a = c / B;
-    const TIn* base = Y + a * L * B + (c - a * B);
+    const bool in = cs + tid % kGC < cend;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int row = row0 + tid / kGC + 8 * u;
-      v[u] = (c < cend && row < L) ? Elem<TIn>::to_f64(base[(int64_t)row * B]) : 0.0;
+      v[u] = (in && row < L) ? col[(int64_t)row * B] : TIn(0);
     }
   }
 }
-__device__ __forceinline__ void gram_store_step(double (*X)[kGP], const double (&v)[8], bool b1) {
+
+// Column walker of a thread for B > 1: c = (a, b) -> pointer to Y[a, 0, b];
+// one division at the start, then steps of kGC columns.
+template <typename TIn>
+struct GramCol {
+  int64_t a, b;
+  __device__ __forceinline__ void start(int64_t c, int64_t B) {
+    a = c / B;
+    b = c - a * B;
+  }
+  __device__ __forceinline__ void step(int64_t B) {
+    b += kGC;
+    while (b >= B) {
+      b -= B;
+      ++a;
+    }
+  }
+  __device__ __forceinline__ const TIn* ptr(const TIn* Y, int L, int64_t B) const {
+    return Y + a * L * B + b;
+  }
+};
+template <typename TIn>
+__device__ __forceinline__ void gram_store_step(double (*X)[kGP], const TIn (&v)[8], bool b1) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
+    const double x = Elem<TIn>::to_f64(v[u]);
     if (b1)
-      X[tid / kGT + 4 * u][tid % kGT] = v[u];
+      X[tid / kGT + 4 * u][tid % kGT] = x;
     else
-      X[tid % kGC][tid / kGC + 8 * u] = v[u];
+      X[tid % kGC][tid / kGC + 8 * u] = x;
   }
 }
 
@@ -78,14 +102,15 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// (4 waves per SIMD for 2- and 4-byte inputs; FP64 raw sets need the
+// registers of 2.)
 // Partial Gram of column chunk `chunk` for tile pair `pair` -> one 64 x 64
 // block of `part` (row index in tile ti, column index in tile tj).  Wave w
 // owns the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of
 // v_mfma_f64_16x16x4_f64: per four columns, lane l supplies row l % 16 of
 // column l / 16 for both operands (A = the ti rows, B = the tj rows), and
 // holds D[l / 16 + 4 r][l % 16] in register r.  16-row blocks entirely past
-// row L are skipped.  The next step's elements are loaded while the current
-// one is multiplied.
+// row L are skipped.  Loads run two steps ahead of the multiplications.
 template <typename TIn>
 __device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int L, int64_t B,
                                                   int64_t C, int64_t cchunk, int T, int npairs,
@@ -104,19 +129,18 @@ __device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int
   d4 acc00 = {0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
   double (*Xb)[kGP] = diag ? Xi : Xj;
 
-  double vi[8], vj[8];
-  gram_load_step<TIn>(vi, Y, L, B, ti * kGT, cbeg, cend);
-  if (!diag) gram_load_step<TIn>(vj, Y, L, B, tj * kGT, cbeg, cend);
+  // steps s = 0, 1, 2, ... of kGC columns; step s's elements are loaded two
+  // steps ahead into raw set s % 2 (loads in step order, one column walker)
+  GramCol<TIn> cw;
+  if (!b1) cw.start(cbeg + threadIdx.x % kGC, B);
+  TIn ri[2][8], rj[2][8];
+  auto load = [&](int set, int64_t cs) {
+    gram_load_step<TIn>(ri[set], Y, L, B, ti * kGT, cs, cend, cw.ptr(Y, L, B));
+    if (!diag) gram_load_step<TIn>(rj[set], Y, L, B, tj * kGT, cs, cend, cw.ptr(Y, L, B));
+    if (!b1) cw.step(B);
+  };
   const int r = lane & 15, k4 = lane >> 4;
-  for (int64_t cs = cbeg; cs < cend; cs += kGC) {
-    __syncthreads();  // the previous step has been multiplied
-    gram_store_step(Xi, vi, b1);
-    if (!diag) gram_store_step(Xj, vj, b1);
-    __syncthreads();
-    if (cs + kGC < cend) {
-      gram_load_step<TIn>(vi, Y, L, B, ti * kGT, cs + kGC, cend);
-      if (!diag) gram_load_step<TIn>(vj, Y, L, B, tj * kGT, cs + kGC, cend);
-    }
+  auto multiply = [&]() {
 #pragma unroll
     for (int k = 0; k < kGC; k += 4) {
       const double a0 = Xi[k + k4][rq + r], a1 = Xi[k + k4][rq + 16 + r];
@@ -126,6 +150,20 @@ __device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int
       if (vi1 && vj0) acc10 = mfma_f64(a1, b0, acc10);
       if (vi1 && vj1) acc11 = mfma_f64(a1, b1v, acc11);
     }
+  };
+  auto step = [&](int set, int64_t cs) {
+    __syncthreads();  // the previous step has been multiplied
+    gram_store_step<TIn>(Xi, ri[set], b1);
+    if (!diag) gram_store_step<TIn>(Xj, rj[set], b1);
+    __syncthreads();
+    if (cs + 2 * kGC < cend) load(set, cs + 2 * kGC);
+    multiply();
+  };
+  load(0, cbeg);
+  if (cbeg + kGC < cend) load(1, cbeg + kGC);
+  for (int64_t cs = cbeg; cs < cend; cs += 2 * kGC) {
+    step(0, cs);
+    if (cs + kGC < cend) step(1, cs + kGC);
   }
   double* out = part + ((int64_t)chunk * npairs + pair) * (kGT * kGT);
   const int i0 = rq + k4, j0 = cq + r;
@@ -139,9 +177,9 @@ __device__ __forceinline__ void gram_partial_body(const TIn* __restrict__ Y, int
 }
 
 template <typename TIn>
-__global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, int L, int64_t B,
-                                                    int64_t C, int64_t cchunk, int T,
-                                                    int npairs, double* __restrict__ part) {
+__global__ __launch_bounds__(256, sizeof(TIn) == 8 ? 2 : 4) void gram_partial(
+    const TIn* __restrict__ Y, int L, int64_t B, int64_t C, int64_t cchunk, int T, int npairs,
+    double* __restrict__ part) {
   __shared__ double Xi[kGC][kGP];
   __shared__ double Xj[kGC][kGP];
   gram_partial_body<TIn>(Y, L, B, C, cchunk, T, npairs, part, blockIdx.x, blockIdx.y, Xi, Xj);
@@ -149,8 +187,8 @@ __global__ __launch_bounds__(256) void gram_partial(const TIn* __restrict__ Y, i
 
 // Grouped Gram (batched HOOI): block b computes item b = (matrix, chunk, pair).
 template <typename TIn>
-__global__ __launch_bounds__(256) void gram_grouped_partial(const GramDesc* __restrict__ mats,
-                                                            const int4* __restrict__ items) {
+__global__ __launch_bounds__(256, sizeof(TIn) == 8 ? 2 : 4) void gram_grouped_partial(
+    const GramDesc* __restrict__ mats, const int4* __restrict__ items) {
   __shared__ double Xi[kGC][kGP];
   __shared__ double Xj[kGC][kGP];
   const int4 w = items[blockIdx.x];
@@ -175,8 +213,19 @@ __device__ __forceinline__ double gram_chunk_sum(const double* __restrict__ part
   const int p = ti * T - ti * (ti - 1) / 2 + (tj - ti);
   const int64_t off = (int64_t)p * (kGT * kGT) + (ii - ti * kGT) * kGT + (jj - tj * kGT);
   const int64_t stride = (int64_t)npairs * (kGT * kGT);
+  // chunks g, g + kRG, ... added in that order; eight loads issued together
   double s = 0.0;
-  for (int ch = g; ch < nchunks; ch += kRG) s += part[ch * stride + off];
+  for (int ch0 = g; ch0 < nchunks; ch0 += 8 * kRG) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int ch = ch0 + u * kRG;
+      v[u] = ch < nchunks ? part[ch * stride + off] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ch0 + u * kRG < nchunks) s += v[u];
+  }
   return s;
 }
 
