@@ -219,6 +219,11 @@ int hooi_batch_error(tk_batch* b, double* rel_err);
  * concatenated (tensor by tensor, mode by mode). */
 int hooi_batch_get_factor(tk_batch* b, int i, int n, double* host);
 int hooi_batch_get_factors(tk_batch* b, double* host);
+/* Replace every factor (layout as hooi_batch_get_factors; host FP64, copied;
+ * TK_ENUMERIC on NaN/Inf).  Solves with p = L (L <= 64) keep their full
+ * eigenbasis from one invocation to the next as a warm start; setting the
+ * factors resets those bases to the identity, so a resumed batch matches an
+ * uninterrupted one to rounding, not bitwise. */
 int hooi_batch_set_factors(tk_batch* b, const double* host);
 /* on = 0: enqueue every iteration eagerly instead of replaying the graph. */
 int hooi_batch_use_graph(tk_batch* b, int on);

@@ -77,6 +77,8 @@ struct tk_batch {
   double* S = nullptr;
   double* ev = nullptr;
   double* eigwork = nullptr;
+  double* basis = nullptr;  // full eigenbases of the p = L solves (EigJob::basis_off)
+  std::vector<EigJob> jobs_h;  // job table (host copy), to restore identity bases
   int* status = nullptr;
   EigJob* jobs_warm = nullptr;
   EigJob* jobs_cold = nullptr;
@@ -116,9 +118,10 @@ struct tk_batch {
     if (st) (void)hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    void* ptrs[] = {ws, Fc, F64a, F64b, S, ev, eigwork, status, jobs_warm, jobs_cold, core,
-                    core_off, normG2, normT2_dev, sumsq_part, ttm_nodes, ttm_items, counters,
-                    gram, gram_items, gram_off, gpart};
+    void* ptrs[] = {ws,        Fc,        F64a,       F64b,     S,          ev,
+                    eigwork,   basis,     status,     jobs_warm, jobs_cold, core,
+                    core_off,  normG2,    normT2_dev, sumsq_part, ttm_nodes, ttm_items,
+                    counters,  gram,      gram_items, gram_off,  gpart};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (st) (void)hipStreamDestroy(st);
@@ -167,7 +170,7 @@ int enqueue_iteration(tk_batch* b) {
   if (int rc = enqueue_pass(b)) return rc;
   for (const auto& c : b->warm_classes)
     TK_HIP(launch_eig(c.count, b->jobs_warm, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64b,
-                      b->ev, b->eigwork, b->status, nullptr, 20, 1e-11, b->st));
+                      b->ev, b->eigwork, b->status, nullptr, 20, 1e-11, b->st, b->basis));
   TK_HIP(launch_copy_f64(b->F64b, b->F64a, b->nF, b->st));
   TK_HIP(launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, b->st));
   return TK_OK;
@@ -498,6 +501,13 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     }
   }
   b->n_jobs = (int)jc.size();
+  // full solves (p = L) keep their eigenbasis between invocations
+  int64_t nbasis = 0;
+  for (auto& j : jc)
+    if (j.p == j.L) {
+      j.basis_off = nbasis;
+      nbasis += (int64_t)j.L * j.L;
+    }
   int64_t work = 0;
   for (auto& j : jc) {
     j.work_off = work;
@@ -541,6 +551,15 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     // boundaries and take each range's own widest cold block
     classes(jc, jw, &b->cold_classes);
   }
+  b->jobs_h = jc;
+  if (nbasis > 0) {
+    std::vector<double> ident;
+    eig_identity_bases(jc, &ident);
+    if ((rc = dalloc_t(&b->basis, (size_t)nbasis))) return bail(rc);
+    if (hipMemcpy(b->basis, ident.data(), sizeof(double) * ident.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return bail(fail(TK_EDEVICE, "basis upload failed"));
+  }
   if ((rc = dalloc_t(&b->eigwork, (size_t)work)) || (rc = dalloc_t(&b->status, (size_t)b->n_jobs)) ||
       (rc = upload(&b->jobs_warm, jw, st)) || (rc = upload(&b->jobs_cold, jc, st)))
     return bail(rc);
@@ -571,7 +590,7 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
   for (size_t k = 0; k < b->cold_classes.size() && e == hipSuccess; ++k) {
     const auto& c = b->cold_classes[k];
     e = launch_eig(c.count, b->jobs_cold, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64a, b->ev,
-                   b->eigwork, b->status, nullptr, 100, 1e-11, st);
+                   b->eigwork, b->status, nullptr, 100, 1e-11, st, b->basis);
   }
   if (e == hipSuccess) e = launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, st);
   if (e == hipSuccess)
@@ -653,6 +672,13 @@ extern "C" int hooi_batch_set_factors(tk_batch* b, const double* host) {
   Handoff handoff(b);
   TK_HIP(hipMemcpyAsync(b->F64a, host, sizeof(double) * b->nF, hipMemcpyHostToDevice, b->st));
   TK_HIP(launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, b->st));
+  std::vector<double> ident;
+  if (b->basis) {
+    // the full solves restart from identity bases, as after initialisation
+    eig_identity_bases(b->jobs_h, &ident);
+    TK_HIP(hipMemcpyAsync(b->basis, ident.data(), sizeof(double) * ident.size(),
+                          hipMemcpyHostToDevice, b->st));
+  }
   TK_HIP(hipStreamSynchronize(b->st));
   return TK_OK;
 }

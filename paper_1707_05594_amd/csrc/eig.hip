@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     const EigJob* __restrict__ jobs, int job0, const double* __restrict__ S_base,
     const double* __restrict__ V0_base, double* __restrict__ F_base, double* __restrict__ ev_base,
     double* __restrict__ work_base, int* __restrict__ status, int* __restrict__ iters_out,
-    int maxit, double tol) {
+    int maxit, double tol, double* __restrict__ basis_base) {
   extern __shared__ double dyn[];
   __shared__ EigSmall small;
   const int mi = job0 + blockIdx.x;
@@ -326,8 +326,9 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
   m.sm = &small;
   EigSmall& sh = small;
 
-  // start block: p = L (full Jacobi) when L <= p_max; warm: the K previous
-  // factors; cold: p_max columns
+  // start block: p = L (full Jacobi) when L <= p_max, from the stored basis
+  // on a warm solve (else the identity); warm: the K previous factors; cold:
+  // p_max columns
   int p;
   if (pmax == L)
     p = L;
@@ -335,13 +336,16 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     p = K;
   else
     p = pmax;
+  double* basis = (p == L && job.basis_off >= 0 && basis_base) ? basis_base + job.basis_off
+                                                                : nullptr;
+  const bool warm_basis = basis && V0;
   bool grown = (p == pmax);
   for (int e = tid; e < L * PS; e += kEigThreads) {
     const int i = e / PS, j = e % PS;
     double v = 0.0;
     if (j < p) {
       if (p == L)
-        v = (i == j) ? 1.0 : 0.0;
+        v = warm_basis ? basis[i * L + j] : ((i == j) ? 1.0 : 0.0);
       else if (V0 && j < K)
         v = V0[(int64_t)i * K + j];
       else
@@ -350,7 +354,7 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     m.V[e] = v;
   }
   __syncthreads();
-  if (p < L) orth<PS>(m, L);
+  if (p < L || warm_basis) orth<PS>(m, L);
 
   int converged = 0;
   int used = 0;
@@ -477,8 +481,10 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     orth<PS>(m, L);
   }
 
-  // ---- output: first K columns, sign rule, eigenvalues
+  // ---- output: the basis (p = L), first K columns with the sign rule, eigenvalues
   const double* V = m.V;
+  if (basis && converged == 1)
+    for (int e = tid; e < L * L; e += kEigThreads) basis[e] = V[(e / L) * PS + e % L];
   for (int j = 0; j < K; ++j) {
     double best = -1.0;
     int bi = 0x7fffffff;
@@ -588,17 +594,18 @@ hipError_t init_lds_limit() {
 template <int PS>
 void launch_ps(int count, const EigJob* jobs_dev, int job0, int Lmax, const double* S_base,
                const double* V0_base, double* F_base, double* ev_base, double* work_base,
-               int* status, int* iters, int maxit, double tol, hipStream_t st) {
+               int* status, int* iters, int maxit, double tol, hipStream_t st,
+               double* basis_base) {
   const bool in_lds = eig_lds_bytes(Lmax, PS, true) <= (size_t)g_lds_limit;
   const size_t lds = eig_lds_bytes(Lmax, PS, in_lds);
   if (in_lds)
     hipLaunchKernelGGL((eig_subspace<PS, true>), dim3(count), dim3(kEigThreads), lds, st,
                        jobs_dev, job0, S_base, V0_base, F_base, ev_base, work_base, status, iters,
-                       maxit, tol);
+                       maxit, tol, basis_base);
   else
     hipLaunchKernelGGL((eig_subspace<PS, false>), dim3(count), dim3(kEigThreads), lds, st,
                        jobs_dev, job0, S_base, V0_base, F_base, ev_base, work_base, status, iters,
-                       maxit, tol);
+                       maxit, tol, basis_base);
 }
 
 }  // namespace
@@ -608,7 +615,7 @@ size_t eig_work_elems(int L, int p) { return (size_t)2 * L * padded(p); }
 hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int pmax,
                       const double* S_base, const double* V0_base, double* F_base,
                       double* ev_base, double* work_base, int* status, int* iters, int maxit,
-                      double tol, hipStream_t st) {
+                      double tol, hipStream_t st, double* basis_base) {
   if (count == 0) return hipSuccess;
   hipError_t e = init_lds_limit();
   if (e != hipSuccess) return e;
@@ -616,7 +623,7 @@ hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int
 #define TK_EIG_CASE(P)                                                                    \
   case P:                                                                                 \
     launch_ps<P>(count, jobs_dev, job0, Lmax, S_base, V0_base, F_base, ev_base, work_base, \
-                 status, iters, maxit, tol, st);                                          \
+                 status, iters, maxit, tol, st, basis_base);                              \
     break;
   switch (PS) {
     TK_EIG_CASE(8)
@@ -635,5 +642,15 @@ hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int
 }
 
 int eig_max_K() { return 48; }
+
+void eig_identity_bases(const std::vector<EigJob>& jobs, std::vector<double>* out) {
+  size_t n = 0;
+  for (const EigJob& j : jobs)
+    if (j.basis_off >= 0) n = std::max(n, (size_t)j.basis_off + (size_t)j.L * j.L);
+  out->assign(n, 0.0);
+  for (const EigJob& j : jobs)
+    if (j.basis_off >= 0)
+      for (int i = 0; i < j.L; ++i) (*out)[(size_t)j.basis_off + (size_t)i * j.L + i] = 1.0;
+}
 
 }  // namespace tk

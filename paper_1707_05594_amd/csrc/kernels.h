@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -86,6 +88,11 @@ hipError_t launch_gram_grouped(int in_dtype, const GramDesc* mats, const int4* i
 struct EigJob {
   int L, K, p, pad_;
   int64_t S_off, V0_off, F_off, ev_off, work_off;
+  // p = L only: the full eigenbasis (L x L row-major) at basis_base +
+  // basis_off, or -1.  A warm solve starts from it (re-orthonormalised) and
+  // every solve writes its final basis back; any orthonormal basis is a valid
+  // start, so callers initialise it to the identity.
+  int64_t basis_off = -1;
 };
 // Jobs [job0, job0 + count) of the device table; Lmax / pmax bound their L and p.
 // Every job of the launch uses the block width padded(pmax): its work area
@@ -95,7 +102,9 @@ struct EigJob {
 hipError_t launch_eig(int count, const EigJob* jobs_dev, int job0, int Lmax, int pmax,
                       const double* S_base, const double* V0_base, double* F_base,
                       double* ev_base, double* work_base, int* status, int* iters, int maxit,
-                      double tol, hipStream_t st);
+                      double tol, hipStream_t st, double* basis_base = nullptr);
+// Identity bases for the p = L jobs of a table (host-built, uploaded by the caller).
+void eig_identity_bases(const std::vector<EigJob>& jobs, std::vector<double>* out);
 int eig_block_size(int L, int K, int64_t rank_bound);
 size_t eig_work_elems(int L, int p);  // global work doubles one job may need
 int eig_max_K();

@@ -115,3 +115,25 @@ def test_batch_rejects_bad_input():
     with pytest.raises(tk.TuckerError) as e:
         tk.Batch([torch.zeros((40, 40, 40), dtype=torch.float32, device=dev)], [(20, 20, 20)])
     assert e.value.code == tk.TK_EUNSUPPORTED
+
+
+def test_resume_from_factors_matches_to_rounding():
+    """Full solves (L <= 64) keep their eigenbasis from one invocation to the
+    next as a warm start; setting the factors restarts those bases from the
+    identity.  Any orthonormal start gives the same eigenvectors up to
+    rounding, so a batch resumed from saved factors follows the uninterrupted
+    run to rounding (the FP32 copies of the factors, hence every leaf, stay
+    equal)."""
+    shapes, host, devs = _batch(8, seed=4)
+    K = [k for _, k in shapes]
+    a = tk.Batch(devs, K)
+    a.iterate(2)
+    F = a.factors()
+    a.iterate(2)
+    b = tk.Batch(devs, K)
+    b.set_factors(F)
+    b.iterate(2)
+    for i, (L, _) in enumerate(shapes):
+        for n in range(len(L)):
+            assert subspace_dist(a.factor(i, n), b.factor(i, n)) < 1e-9, (i, n)
+    np.testing.assert_allclose(a.error(), b.error(), rtol=1e-9)
