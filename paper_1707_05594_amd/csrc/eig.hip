@@ -54,8 +54,10 @@ struct EigSmall {
   double theta[kEigPMax];
   double dscale[kEigPMax];
   double red[4 * kEigPMax];
-  double cs_c[kEigPMax], cs_s[kEigPMax];
-  int partner[kEigPMax];
+  double cs_c[kEigPMax];  // Cholesky reciprocals (cholqr_pass)
+  // rotations of one Jacobi round: pair q = (pair_a[q] < pair_b[q]), cosine, sine
+  int pair_a[kEigPMax / 2], pair_b[kEigPMax / 2];
+  double pair_c[kEigPMax / 2], pair_s[kEigPMax / 2];
   int perm[kEigPMax];
   int flag;
   double minpiv;
@@ -205,20 +207,24 @@ __device__ __forceinline__ void orth(EigMem<PS>& m, int L) {
 }
 
 // Cyclic Jacobi (round-robin pairs) on H (PS x PS) by the whole block; Z
-// accumulates the rotations.
+// accumulates the rotations.  A round rotates PS / 2 disjoint pairs at once:
+// with J the product of the round's rotations, H <- J^T H J is applied by 2 x 2
+// blocks -- the block of row pair P and column pair R depends only on its own
+// four entries and the two pairs' rotations, so one thread reads it once and
+// rewrites it in place -- and Z <- Z J by the two columns of each pair.
 template <int PS>
 __device__ __forceinline__ void jacobi_block(EigMem<PS>& m, int maxsweep) {
+  constexpr int NP = PS / 2;
   EigSmall& sh = *m.sm;
   const int tid = threadIdx.x;
   double* Z = m.Z;
+  double* H = m.H;
   for (int e = tid; e < PS * PS; e += kEigThreads) Z[e] = (e / PS == e % PS) ? 1.0 : 0.0;
   __syncthreads();
-  double* Hc = m.H;
-  double* Hn = m.H2;
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = tid; e < PS * PS; e += kEigThreads) {
-      const double v = Hc[e];
+      const double v = H[e];
       if (e / PS == e % PS)
         dia += v * v;
       else
@@ -238,60 +244,56 @@ __device__ __forceinline__ void jacobi_block(EigMem<PS>& m, int maxsweep) {
     // exact to far below the residual test that decides convergence
     if (off <= 1e-26 * dia || off == 0.0) break;
     for (int r = 0; r < PS - 1; ++r) {
-      if (tid < PS / 2) {
-        const int lane = tid;
-        auto slot = [&](int s) { return s == 0 ? 0 : 1 + (s - 1 + r) % (PS - 1); };
-        int a = slot(lane), b = slot(PS - 1 - lane);
+      if (tid < NP) {
+        auto slot = [&](int q) { return q == 0 ? 0 : 1 + (q - 1 + r) % (PS - 1); };
+        int a = slot(tid), b = slot(PS - 1 - tid);
         if (a > b) {
           const int t = a;
           a = b;
           b = t;
         }
         double c = 1.0, s = 0.0;
-        const double apq = Hc[a * PS + b];
+        const double apq = H[a * PS + b];
         if (apq != 0.0) {
-          const double tau = (Hc[b * PS + b] - Hc[a * PS + a]) / (2.0 * apq);
+          const double tau = (H[b * PS + b] - H[a * PS + a]) / (2.0 * apq);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
         }
-        // rotation J: J[a][a] = c, J[b][a] = -s, J[a][b] = s, J[b][b] = c
-        sh.partner[a] = b;
-        sh.cs_c[a] = c;
-        sh.cs_s[a] = -s;
-        sh.partner[b] = a;
-        sh.cs_c[b] = c;
-        sh.cs_s[b] = s;
+        // rotation: J[a][a] = c, J[b][a] = -s, J[a][b] = s, J[b][b] = c
+        sh.pair_a[tid] = a;
+        sh.pair_b[tid] = b;
+        sh.pair_c[tid] = c;
+        sh.pair_s[tid] = s;
       }
       __syncthreads();
-      for (int e = tid; e < PS * PS; e += kEigThreads) {
-        const int x = e / PS, y = e % PS;
-        const int xp = sh.partner[x], yp = sh.partner[y];
-        const double ax = sh.cs_c[x], bx = sh.cs_s[x], ay = sh.cs_c[y], by = sh.cs_s[y];
-        double v = ax * ay * Hc[x * PS + y] + ax * by * Hc[x * PS + yp] +
-                   bx * ay * Hc[xp * PS + y] + bx * by * Hc[xp * PS + yp];
-        if (xp == y) v = 0.0;  // the annihilated pair
-        Hn[e] = v;
+      for (int w = tid; w < NP * NP; w += kEigThreads) {
+        const int P = w / NP, R = w % NP;
+        const int aP = sh.pair_a[P], bP = sh.pair_b[P], aR = sh.pair_a[R], bR = sh.pair_b[R];
+        const double cP = sh.pair_c[P], sP = sh.pair_s[P], cR = sh.pair_c[R], sR = sh.pair_s[R];
+        const double haa = H[aP * PS + aR], hab = H[aP * PS + bR];
+        const double hba = H[bP * PS + aR], hbb = H[bP * PS + bR];
+        // rows: x = a takes (c, -s) with its partner, x = b takes (c, +s); columns alike
+        double naa = cP * cR * haa - cP * sR * hab - sP * cR * hba + sP * sR * hbb;
+        double nab = cP * cR * hab + cP * sR * haa - sP * cR * hbb - sP * sR * hba;
+        double nba = cP * cR * hba - cP * sR * hbb + sP * cR * haa - sP * sR * hab;
+        const double nbb = cP * cR * hbb + cP * sR * hba + sP * cR * hab + sP * sR * haa;
+        if (P == R) nab = nba = 0.0;  // the annihilated pair
+        H[aP * PS + aR] = naa;
+        H[aP * PS + bR] = nab;
+        H[bP * PS + aR] = nba;
+        H[bP * PS + bR] = nbb;
       }
-      // Z <- Z J: a thread owns (row i, pair) updates for the first member of each pair
-      for (int e = tid; e < PS * PS; e += kEigThreads) {
-        const int i = e / PS, y = e % PS;
-        const int yp = sh.partner[y];
-        if (yp > y) {
-          const double zy = Z[i * PS + y], zyp = Z[i * PS + yp];
-          Z[i * PS + y] = sh.cs_c[y] * zy + sh.cs_s[y] * zyp;
-          Z[i * PS + yp] = sh.cs_c[yp] * zyp + sh.cs_s[yp] * zy;
-        }
+      for (int w = tid; w < PS * NP; w += kEigThreads) {
+        const int i = w / NP, P = w % NP;
+        const int a = sh.pair_a[P], b = sh.pair_b[P];
+        const double c = sh.pair_c[P], s = sh.pair_s[P];
+        const double za = Z[i * PS + a], zb = Z[i * PS + b];
+        Z[i * PS + a] = c * za - s * zb;
+        Z[i * PS + b] = c * zb + s * za;
       }
       __syncthreads();
-      double* t = Hc;
-      Hc = Hn;
-      Hn = t;
     }
-  }
-  if (Hc != m.H) {
-    for (int e = tid; e < PS * PS; e += kEigThreads) m.H[e] = Hc[e];
-    __syncthreads();
   }
 }
 
