@@ -63,6 +63,11 @@ struct tk_batch {
   std::vector<double> normT2;
   hipStream_t user = nullptr, st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // eigensolve classes run concurrently: forked from `st` onto kAux streams
+  // (default priority) and joined back before the factor update
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   int ncu = 256;
   int blocks_per_cu = 4;
 
@@ -125,6 +130,11 @@ struct tk_batch {
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (st) (void)hipStreamDestroy(st);
+    for (int k = 0; k < kAux; ++k) {
+      if (aux[k]) (void)hipStreamDestroy(aux[k]);
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
   }
@@ -168,9 +178,22 @@ int enqueue_pass(tk_batch* b) {
 // One HOOI invocation for every tensor: pass, warm eigensolves, factor update.
 int enqueue_iteration(tk_batch* b) {
   if (int rc = enqueue_pass(b)) return rc;
-  for (const auto& c : b->warm_classes)
+  // classes touch disjoint jobs (S, work areas, bases, outputs): fork them over
+  // the auxiliary streams so that small classes share the chip
+  const int nc = (int)b->warm_classes.size();
+  const int used = std::min(nc, (int)tk_batch::kAux);
+  if (used > 0) TK_HIP(hipEventRecord(b->ev_fork, b->st));
+  for (int k = 0; k < used; ++k) TK_HIP(hipStreamWaitEvent(b->aux[k], b->ev_fork, 0));
+  for (int q = 0; q < nc; ++q) {
+    const auto& c = b->warm_classes[q];
     TK_HIP(launch_eig(c.count, b->jobs_warm, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64b,
-                      b->ev, b->eigwork, b->status, nullptr, 20, 1e-11, b->st, b->basis));
+                      b->ev, b->eigwork, b->status, nullptr, 20, 1e-11,
+                      b->aux[q % tk_batch::kAux], b->basis));
+  }
+  for (int k = 0; k < used; ++k) {
+    TK_HIP(hipEventRecord(b->ev_join[k], b->aux[k]));
+    TK_HIP(hipStreamWaitEvent(b->st, b->ev_join[k], 0));
+  }
   TK_HIP(launch_copy_f64(b->F64b, b->F64a, b->nF, b->st));
   TK_HIP(launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, b->st));
   return TK_OK;
@@ -231,10 +254,17 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
         hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
       return bail(fail(TK_EDEVICE, "stream/event creation failed"));
     }
+    for (int k = 0; k < tk_batch::kAux; ++k)
+      if (hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(TK_EDEVICE, "stream/event creation failed"));
+      }
   }
   // ---- shapes and plans (one DP plan per distinct shape)
   std::map<std::vector<int64_t>, Tree> plans;
