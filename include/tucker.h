@@ -227,7 +227,7 @@ int hooi_batch_get_factors(tk_batch* b, double* host);
 int hooi_batch_set_factors(tk_batch* b, const double* host);
 /* on = 0: enqueue every iteration eagerly instead of replaying the graph. */
 int hooi_batch_use_graph(tk_batch* b, int on);
-/* Autotuner: times the tree levels with 1, 2, 4 and 8 persistent blocks per
+/* Autotuner: times the tree levels with 1, 2, 3 and 4 persistent blocks per
  * CU, keeps the fastest (ms: NULL or 4 floats) and re-captures the graph. */
 int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms);
 /* Multiply-adds and algorithmic bytes (inputs read once, outputs written

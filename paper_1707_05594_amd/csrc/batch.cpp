@@ -733,7 +733,7 @@ extern "C" int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms) {
   clear_error();
   if (!b) return fail(TK_EINVAL, "batch is null");
   Handoff handoff(b);
-  static const int cand[4] = {1, 2, 4, 8};
+  static const int cand[4] = {1, 2, 3, 4};  // the grouped kernel holds 3 blocks per CU
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TK_HIP(hipEventCreate(&e0));
   TK_HIP(hipEventCreate(&e1));

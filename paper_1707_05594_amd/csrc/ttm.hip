@@ -799,9 +799,11 @@ __global__ __launch_bounds__(256) void ttm_tile_f32(const TIn* __restrict__ in,
 // Grouped TTM for batched HOOI: the (node, tile) items of many nodes, drained
 // from a device queue by a persistent grid.  Each block takes the next item
 // with one atomic increment; every block leaves once the queue is empty.
-// Nodes have K <= 16 (one K-chunk of four groups) and L <= Lmax.
+// Nodes have K <= 16 (one K-chunk of four groups) and L <= Lmax.  Held to
+// three waves per SIMD (the LDS of a block allows three per CU), which the
+// bodies reach without spilling.
 template <typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_grouped(const TtmNodeDesc* __restrict__ nodes,
+__global__ __launch_bounds__(256, 3) void ttm_grouped(const TtmNodeDesc* __restrict__ nodes,
                                                    const int2* __restrict__ items, int n_items,
                                                    int* __restrict__ counter) {
   extern __shared__ float smem[];
