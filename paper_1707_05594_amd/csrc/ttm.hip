@@ -224,6 +224,40 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
   wide_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
+// Slab-aligned variant for runs of B (<= 256) that are not whole 128-byte
+// lines while every slab In[a, :, :] starts on a line: a wave takes
+// 64 / (B / 4) whole slabs, B / 4 lanes each (the rest idle), so no cache
+// line is shared with another wave and the input can be streamed.
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_wide_slab_f32(const TIn* __restrict__ in,
+                                                         const float* __restrict__ F,
+                                                         float* __restrict__ out, int64_t A,
+                                                         int L, int64_t B, int Kt) {
+  extern __shared__ float smem[];
+  const int k0 = blockIdx.y * 4 * KG;
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int lpa = (int)(B / 4), apw = 64 / lpa;
+  const int64_t a0 = ((int64_t)blockIdx.x * 4 + wave) * apw;
+  if (a0 >= A) return;  // whole wave idle
+  const int al = lane / lpa;
+  const bool active = al < apw && a0 + al < A;
+  // idle lanes read slab a0 (always in bounds) and store nothing
+  const int64_t a = active ? a0 + al : a0;
+  const int64_t b = active ? 4 * (lane % lpa) : 0;
+  const TIn* p = in + (a * L) * B + b;
+  const float* ft = smem + (lane & 3) * L * KG;
+  f4 acc[KG][4];
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  wide_chain<KG, TIn, NT>(p, B, ft, 0, L, acc);
+  if (active) wide_store<KG>(out, a, b, B, Kt, k0, acc);
+}
+
 // ------------------------------------------------------------------- row path --
 // B == 1 (the last mode): Out[a, k] = sum_l In[a, l] F[l, k], rows of In
 // contiguous.  In a 4x4x1 MFMA the B operand of lane i is a value of its own
@@ -965,13 +999,29 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
     const size_t lds = (size_t)16 * L * KG;
     dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
     // runs of B that are not whole 128-byte lines share their boundary lines
-    // with a neighbouring wave: normal loads keep those lines cached
-    if (NT && (B * sizeof(TIn)) % 128 == 0)
+    // with a neighbouring wave: whole slabs per wave when that keeps >= 3/4
+    // of the lanes busy and slabs start on lines (then streaming is safe),
+    // else normal loads, which keep those lines cached
+    const bool line_runs = (B * sizeof(TIn)) % 128 == 0;
+    const int64_t lpa = B / 4;
+    const bool slab = !line_runs && B <= 256 && (64 / lpa) * lpa >= 48 &&
+                      ((int64_t)L * B * sizeof(TIn)) % 128 == 0;
+    if (slab) {
+      const int64_t apb = 4 * (64 / lpa);  // slabs per block
+      dim3 sgrid((unsigned)((A + apb - 1) / apb), (unsigned)chunks);
+      if (NT)
+        hipLaunchKernelGGL((ttm_wide_slab_f32<KG, TIn, true>), sgrid, dim3(256), lds, st, in, F,
+                           out, A, L, B, K);
+      else
+        hipLaunchKernelGGL((ttm_wide_slab_f32<KG, TIn, false>), sgrid, dim3(256), lds, st, in, F,
+                           out, A, L, B, K);
+    } else if (NT && line_runs) {
       hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, true>), grid, dim3(256), lds, st, in, F, out, C,
                          L, B, K);
-    else
+    } else {
       hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, false>), grid, dim3(256), lds, st, in, F, out, C,
                          L, B, K);
+    }
   } else if (path == Path::kWideSplitL) {
     if (KG > kSplitLMaxKG || splitl_lds(L, KG) > (size_t)kLdsBudget) return hipErrorInvalidValue;
     const int64_t C = A * B;

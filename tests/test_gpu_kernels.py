@@ -41,6 +41,8 @@ TTM_CASES = [
     (5, 1, 64, 3),       # small wide grid (split L): one row, three waves idle
     (1, 300, 32, 24),    # small wide grid: K over six chunks
     (200, 200, 400, 20), # small wide grid: 313 blocks of 256 columns
+    (13201, 32, 20, 6),  # slab-aligned wide path: 80-byte runs, 12 slabs per wave, ragged A
+    (1320, 40, 200, 20), # slab-aligned wide path: one 800-byte-run slab per wave
 ]
 
 
