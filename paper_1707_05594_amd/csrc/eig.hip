@@ -380,7 +380,8 @@ __global__ __launch_bounds__(kEigThreads) void eig_subspace(
     double* W = m.W;
     // ---- W = S V (S symmetric: threads walk rows i, reading S[l][i] coalesced),
     // in column chunks of kCW so the accumulators stay in registers
-    constexpr int kCW = PS % 16 == 0 ? 16 : 8;  // divides PS (a multiple of 8)
+    // one pass over S for blocks up to 32 columns, else chunks that divide PS
+    constexpr int kCW = PS <= 32 ? PS : (PS % 16 == 0 ? 16 : 8);
     static_assert(PS % kCW == 0, "column chunks must tile the padded width");
     for (int i = tid; i < L; i += kEigThreads) {
       for (int c0 = 0; c0 < PS; c0 += kCW) {
