@@ -1001,10 +1001,12 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
     // runs of B that are not whole 128-byte lines share their boundary lines
     // with a neighbouring wave: whole slabs per wave when that keeps >= 3/4
     // of the lanes busy and slabs start on lines (then streaming is safe),
-    // else normal loads, which keep those lines cached
+    // else normal loads, which keep those lines cached.  Slabs only for FP32
+    // input: with 8 bytes per lane and idle lanes, BF16 rows load too little
+    // per instruction (measured slower than normal loads).
     const bool line_runs = (B * sizeof(TIn)) % 128 == 0;
     const int64_t lpa = B / 4;
-    const bool slab = !line_runs && B <= 256 && (64 / lpa) * lpa >= 48 &&
+    const bool slab = sizeof(TIn) == 4 && !line_runs && B <= 256 && (64 / lpa) * lpa >= 48 &&
                       ((int64_t)L * B * sizeof(TIn)) % 128 == 0;
     if (slab) {
       const int64_t apb = 4 * (64 / lpa);  // slabs per block
