@@ -528,8 +528,8 @@ __device__ __forceinline__ void split4(float x0, float x1, float x2, float x3, u
   lo.y = pack_bf16(x2 - bf16_low_f32(hi.y), x3 - bf16_high_f32(hi.y));
 }
 
-template <int KG, bool X3>
-__device__ __forceinline__ void stage_factor_bf16(uint2* FH, uint2* FL,
+template <int KG, bool X3, bool F3 = false>
+__device__ __forceinline__ void stage_factor_bf16(uint2* FH, uint2* FL, uint2* FL2,
                                                   const float* __restrict__ F, int L, int LB,
                                                   int Kt, int k0) {
   const int total = 4 * LB * KG;
@@ -549,14 +549,25 @@ __device__ __forceinline__ void stage_factor_bf16(uint2* FH, uint2* FL,
     split4(f[0], f[1], f[2], f[3], hi, lo);
     FH[e] = hi;
     if (X3) FL[e] = lo;
+    if constexpr (F3) {
+      // third term: f - hi - lo (both differences exact in FP32) is exactly a
+      // bfloat16, so hi + lo + lo2 reproduces the FP32 factor bit for bit
+      uint2 lo2;
+      lo2.x = pack_bf16(f[0] - bf16_low_f32(hi.x) - bf16_low_f32(lo.x),
+                        f[1] - bf16_high_f32(hi.x) - bf16_high_f32(lo.x));
+      lo2.y = pack_bf16(f[2] - bf16_low_f32(hi.y) - bf16_low_f32(lo.y),
+                        f[3] - bf16_high_f32(hi.y) - bf16_high_f32(lo.y));
+      FL2[e] = lo2;
+    }
   }
 }
 
 // One block of four rows x[q] (q = l mod 4) of the lane's four columns:
 // column j's operand is the four values x[0..3][j].
-template <int KG, bool X3, bool kSplitIn>
+template <int KG, bool X3, bool kSplitIn, bool F3 = false>
 __device__ __forceinline__ void wide_bf16_block(f4 (&acc)[KG][4], const f4 (&x)[4],
-                                                const uint2* fh, const uint2* fl) {
+                                                const uint2* fh, const uint2* fl,
+                                                const uint2* fl2 = nullptr) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     uint2 bh, bl;
@@ -569,12 +580,13 @@ __device__ __forceinline__ void wide_bf16_block(f4 (&acc)[KG][4], const f4 (&x)[
         acc[g][j] = mfma4x4x4bf16(as_s4(fl[g]), as_s4(bh), acc[g][j]);
         if (kSplitIn) acc[g][j] = mfma4x4x4bf16(as_s4(ah), as_s4(bl), acc[g][j]);
       }
+      if (F3) acc[g][j] = mfma4x4x4bf16(as_s4(fl2[g]), as_s4(bh), acc[g][j]);
     }
   }
 }
 
 // Wide path (B % 4 == 0): lane owns columns c0 + 4i .. c0 + 4i + 3.
-template <int KG, typename TIn, bool NT, bool X3, bool OutBF16>
+template <int KG, typename TIn, bool NT, bool X3, bool OutBF16, bool F3 = false>
 __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
                                                      const float* __restrict__ F,
                                                      void* __restrict__ out_, int64_t C, int L,
@@ -583,8 +595,9 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
   const int LB = (L + 3) / 4;
   uint2* FH = sfb;
   uint2* FL = sfb + 4 * LB * KG;
+  uint2* FL2 = sfb + 8 * LB * KG;
   const int k0 = blockIdx.y * 4 * KG;
-  stage_factor_bf16<KG, X3>(FH, FL, F, L, LB, Kt, k0);
+  stage_factor_bf16<KG, X3, F3>(FH, FL, FL2, F, L, LB, Kt, k0);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -596,6 +609,7 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
   const TIn* p = in + (a * L) * B + b;
   const uint2* fh = FH + (lane & 3) * LB * KG;
   const uint2* fl = FL + (lane & 3) * LB * KG;
+  const uint2* fl2 = FL2 + (lane & 3) * LB * KG;
   constexpr bool kSplitIn = X3 && std::is_same<TIn, float>::value;
 
   f4 acc[KG][4];
@@ -617,7 +631,8 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      wide_bf16_block<KG, X3, kSplitIn>(acc, x[u], fh + (lb + u) * KG, fl + (lb + u) * KG);
+      wide_bf16_block<KG, X3, kSplitIn, F3>(acc, x[u], fh + (lb + u) * KG, fl + (lb + u) * KG,
+                                            fl2 + (lb + u) * KG);
   }
   for (; lb < LB; ++lb) {  // remaining blocks, the last one possibly ragged
     f4 x[4];
@@ -626,7 +641,7 @@ __global__ __launch_bounds__(256) void ttm_wide_bf16(const TIn* __restrict__ in,
       const int l = 4 * lb + q;
       x[q] = l < L ? load4_f32<NT>(p + (int64_t)l * B) : f4{0.f, 0.f, 0.f, 0.f};
     }
-    wide_bf16_block<KG, X3, kSplitIn>(acc, x, fh + lb * KG, fl + lb * KG);
+    wide_bf16_block<KG, X3, kSplitIn, F3>(acc, x, fh + lb * KG, fl + lb * KG, fl2 + lb * KG);
   }
   if (!active) return;
   const int64_t q0 = (a * Kt) * B + b;
@@ -676,7 +691,7 @@ __global__ __launch_bounds__(256) void ttm_rows_bf16(const TIn* __restrict__ in,
   uint2* FH = sfb;
   uint2* FL = sfb + 4 * LB * KG;
   const int k0 = blockIdx.y * 4 * KG;
-  stage_factor_bf16<KG, X3>(FH, FL, F, L, LB, Kt, k0);
+  stage_factor_bf16<KG, X3>(FH, FL, nullptr, F, L, LB, Kt, k0);
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t wave_row0 = (int64_t)blockIdx.x * 256 + (threadIdx.x & ~63);
@@ -1120,44 +1135,46 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
 // wide kernel (it spills); wider K is covered by more chunks.
 constexpr int kWideBf16MaxKG = 12;
 
-template <typename TIn, int KG, bool NT, bool X3, bool OutBF16>
+template <typename TIn, int KG, bool NT, bool X3, bool OutBF16, bool F3 = false>
 hipError_t launch_bf16_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, const float* F,
                           int K, void* out, hipStream_t st) {
   const int chunks = (K + 4 * KG - 1) / (4 * KG);
-  const size_t lds = (size_t)32 * ((L + 3) / 4) * KG * (X3 ? 2 : 1);
+  const size_t lds = (size_t)32 * ((L + 3) / 4) * KG * (F3 ? 3 : X3 ? 2 : 1);
   if (path == Path::kWide) {
     if constexpr (KG <= kWideBf16MaxKG) {
       const int64_t C = A * B;
       dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
-      hipLaunchKernelGGL((ttm_wide_bf16<KG, TIn, NT, X3, OutBF16>), grid, dim3(256), lds, st, in,
-                         F, out,
-                         C, L, B, K);
+      hipLaunchKernelGGL((ttm_wide_bf16<KG, TIn, NT, X3, OutBF16, F3>), grid, dim3(256), lds, st,
+                         in, F, out, C, L, B, K);
     } else {
       return hipErrorInvalidValue;  // not reached: launch_bf16 caps the wide KG
     }
   } else {
+    if constexpr (F3) return hipErrorInvalidValue;  // the exact split runs the wide kernel only
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
     hipLaunchKernelGGL((ttm_rows_bf16<KG, TIn, NT, X3, OutBF16>), grid, dim3(256), lds, st, in, F,
-                       out,
-                       A, L, K);
+                       out, A, L, K);
   }
   return hipGetLastError();
 }
 
-template <typename TIn, bool NT, bool X3, bool OutBF16>
+template <typename TIn, bool NT, bool X3, bool OutBF16, bool F3 = false>
 hipError_t launch_bf16_nt(Path path, int kg, const TIn* in, int64_t A, int L, int64_t B,
                           const float* F, int K, void* out, hipStream_t st) {
+#define TK_BF16_KG(G) \
+  return launch_bf16_kg<TIn, G, NT, X3, OutBF16, F3>(path, in, A, L, B, F, K, out, st)
   switch (kg) {
-    case 1: return launch_bf16_kg<TIn, 1, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 2: return launch_bf16_kg<TIn, 2, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 3: return launch_bf16_kg<TIn, 3, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 4: return launch_bf16_kg<TIn, 4, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 5: return launch_bf16_kg<TIn, 5, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 6: return launch_bf16_kg<TIn, 6, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 8: return launch_bf16_kg<TIn, 8, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    case 12: return launch_bf16_kg<TIn, 12, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
-    default: return launch_bf16_kg<TIn, 16, NT, X3, OutBF16>(path, in, A, L, B, F, K, out, st);
+    case 1: TK_BF16_KG(1);
+    case 2: TK_BF16_KG(2);
+    case 3: TK_BF16_KG(3);
+    case 4: TK_BF16_KG(4);
+    case 5: TK_BF16_KG(5);
+    case 6: TK_BF16_KG(6);
+    case 8: TK_BF16_KG(8);
+    case 12: TK_BF16_KG(12);
+    default: TK_BF16_KG(16);
   }
+#undef TK_BF16_KG
 }
 
 // BF16 / split-BF16 compute.  Nodes that need the tile path (B not a multiple
@@ -1176,7 +1193,7 @@ bool bf16_kernel_applies(const TIn* in, const void* out, int64_t L, int64_t B, i
 template <typename TIn>
 hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                        void* out, bool stream_in, bool x3, bool out_bf16, int tile,
-                       hipStream_t st) {
+                       hipStream_t st, bool f3 = false) {
   const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, (float*)out, L, B);
   // the BF16 row kernel reads four consecutive l per lane: L % 4 == 0, aligned
   if (!bf16_kernel_applies(in, out, L, B, tile)) {
@@ -1184,7 +1201,7 @@ hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* 
     return launch_f32<TIn>(in, A, L, B, F, K, (float*)out, stream_in, tile, st);
   }
   if (out_bf16 && x3) return hipErrorInvalidValue;
-  const int per_group = 32 * ((L + 3) / 4) * (x3 ? 2 : 1);  // LDS bytes per K-group
+  const int per_group = 32 * ((L + 3) / 4) * (f3 ? 3 : x3 ? 2 : 1);  // LDS bytes per K-group
   int kg_cap = std::max(1, kLdsBudget / per_group);
   if (path == Path::kWide) kg_cap = std::min(kg_cap, kWideBf16MaxKG);
   int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
@@ -1192,6 +1209,17 @@ hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* 
   // a run (B columns, or a row of L) that is not a whole number of 128-byte
   // lines shares its boundary lines with a neighbouring wave: normal loads
   if ((path == Path::kWide ? B : (int64_t)L) * (int64_t)sizeof(TIn) % 128 != 0) stream_in = false;
+  if (f3) {
+    // exact three-term factor split on BF16 input (wide path only)
+    if constexpr (std::is_same<TIn, uint16_t>::value) {
+      if (path != Path::kWide || out_bf16) return hipErrorInvalidValue;
+      if (stream_in)
+        return launch_bf16_nt<TIn, true, true, false, true>(path, kg, in, A, L, B, F, K, out, st);
+      return launch_bf16_nt<TIn, false, true, false, true>(path, kg, in, A, L, B, F, K, out, st);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (stream_in) {
     if (x3) return launch_bf16_nt<TIn, true, true, false>(path, kg, in, A, L, B, F, K, out, st);
     if (out_bf16)
@@ -1320,8 +1348,17 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
                              (float*)out, stream_in, tile, st);
-  return launch_f32<uint16_t>((const uint16_t*)in, A, (int)L, B, (const float*)F, (int)K,
-                              (float*)out, stream_in, tile, st);
+  // FP32 compute on BF16 input: on wide grids that fill the chip, BF16 MFMAs
+  // with the factor split exactly into three bfloat16 terms (the products of
+  // bfloat16 pairs are exact in FP32, so this matches an FP32 MFMA chain up
+  // to the order of the FP32 accumulation); otherwise the FP32 kernels
+  const uint16_t* in16 = (const uint16_t*)in;
+  if (tile == TK_TILE_AUTO && choose_path(in16, (const float*)out, L, B) == Path::kWide &&
+      grid_blocks(Path::kWide, A, B) >= 256)
+    return launch_bf16<uint16_t>(in16, A, (int)L, B, (const float*)F, (int)K, out, stream_in,
+                                 true, false, tile, st, true);
+  return launch_f32<uint16_t>(in16, A, (int)L, B, (const float*)F, (int)K, (float*)out,
+                              stream_in, tile, st);
 }
 
 }  // namespace tk
