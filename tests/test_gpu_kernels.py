@@ -253,3 +253,23 @@ def test_eig_flat_trailing_spectrum(L, K):
             np.testing.assert_allclose(ev[m], wr, rtol=1e-12, atol=1e-12 * wr[0])
             assert np.linalg.norm(S[m] @ F[m] - F[m] * ev[m]) <= 1e-11 * wr[0]
             assert np.linalg.norm(F[m].T @ F[m] - np.eye(K)) <= 1e-13
+
+
+def test_fp32_compute_on_bf16_input_reproduces_24_bit_factors():
+    """FP32 compute on BF16 input runs BF16 MFMAs with the factor split into
+    three bfloat16 terms, which together hold all 24 bits of an FP32 entry.
+    With f = 1 + 2^-10 + 2^-20 (its third term 2^-20 is nonzero) and an
+    all-ones input, every output is 8 f exactly (all partial sums k f fit in
+    24 bits); a two-term split would lose 8 * 2^-20.  The grid (262144 columns
+    of L = 8) is wide enough for the split path."""
+    torch, dev = torch_dev()
+    A, L, B, K = 1, 8, 262144, 4
+    ones = torch.ones((A, L, B), dtype=torch.bfloat16, device=dev)
+    f = np.float32(1.0 + 2.0 ** -10 + 2.0 ** -20)
+    F = np.full((L, K), f, dtype=np.float32)
+    out = torch.empty((A, K, B), dtype=torch.float32, device=dev)
+    tk.ttm(ones, A, L, B, to_dev(F), K, out)
+    torch.cuda.synchronize()
+    expect = np.float32(8.0 * float(f))
+    assert float(expect) == 8.0 * float(f)  # exact in FP32
+    np.testing.assert_array_equal(out.cpu().numpy(), np.full((A, K, B), expect, np.float32))
