@@ -298,8 +298,12 @@ int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute, doubl
  * [A, K, B] of FP64 (compute FP64) or FP32.  K <= 4096; L <= 512 for
  * TK_C_FP64, L <= 2048 otherwise.  In and Out must not overlap.
  * TK_C_BF16 / TK_C_BF16X3 round (split) In and F to bfloat16 on the fly; a
- * node whose B is not a multiple of 4 (or B == 1 with L not a multiple of 4)
- * is computed with FP32 operands instead, which is at least as accurate.
+ * node whose B is not a multiple of 4 (or B == 1 with L not a multiple of 4),
+ * or a B % 4 == 0 node of fewer than 256 x 1024 columns (A * B), is computed
+ * with FP32 operands instead, which is at least as accurate.  TK_C_FP32 on
+ * BF16 input with at least 256 x 1024 such columns runs BF16 MFMAs with the
+ * factor split exactly into three bfloat16 terms (FP32 results up to the
+ * order of accumulation).
  * Errors: TK_EINVAL (null pointer, size < 1, unknown code), TK_EUNSUPPORTED
  * (dtype/compute pair or size limit), TK_EDEVICE (launch failure). */
 int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,

@@ -596,14 +596,14 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
         int64_t A, Lu, B;
         view(s, nd.pre_mask, nd.mode, &A, &Lu, &B);
         const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
-        bool ok = ttm_bf16_output_ok(c->in_dtype_of(u), TK_C_BF16, in, Lu, B,
+        bool ok = ttm_bf16_output_ok(c->in_dtype_of(u), TK_C_BF16, in, A, Lu, B,
                                      c->wsp(c->node_off[u]), c->node_tile[u]);
         for (size_t v = 0; v < nodes.size() && ok; ++v) {
           if (nodes[v].parent != u) continue;
           int64_t Av, Lv, Bv;
           view(s, nodes[v].pre_mask, nodes[v].mode, &Av, &Lv, &Bv);
           ok = c->node_compute[v] == TK_C_BF16 &&
-               ttm_bf16_output_ok(TK_BF16, TK_C_BF16, c->wsp(c->node_off[u]), Lv, Bv,
+               ttm_bf16_output_ok(TK_BF16, TK_C_BF16, c->wsp(c->node_off[u]), Av, Lv, Bv,
                                   c->wsp(c->node_off[v]), c->node_tile[v]);
         }
         if (ok) dt = TK_BF16;

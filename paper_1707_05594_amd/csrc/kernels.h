@@ -17,8 +17,8 @@ namespace tk {
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
                       const void* F, int64_t K, void* out, hipStream_t st,
                       bool stream_in = false, int tile = 0, int out_dtype = TK_F32);
-bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t L, int64_t B,
-                        const void* out, int tile);
+bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t A, int64_t L,
+                        int64_t B, const void* out, int tile);
 int ttm_max_L();
 
 // Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.

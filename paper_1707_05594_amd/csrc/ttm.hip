@@ -1182,12 +1182,18 @@ hipError_t launch_bf16_nt(Path path, int kg, const TIn* in, int64_t A, int L, in
 // at least as accurate as the mode asks for.
 // True when a TK_C_BF16 node with these operands runs a BF16 kernel (wide or
 // row), which can also write its output in BF16.
+// Wide grids too small to fill the chip run the FP32 split-L kernel instead
+// (it reads the input once; the BF16 kernel would re-read it per K-chunk).
 template <typename TIn>
-bool bf16_kernel_applies(const TIn* in, const void* out, int64_t L, int64_t B, int tile) {
+bool bf16_kernel_applies(const TIn* in, const void* out, int64_t A, int64_t L, int64_t B,
+                         int tile) {
   if (tile == TK_TILE_STAGED) return false;
   const Path path = choose_path(in, (const float*)out, L, B);
   const bool rows_ok = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
-  return path == Path::kWide || (path == Path::kRows && rows_ok);
+  const bool small_wide = grid_blocks(Path::kWide, A, B) < 256 && splitl_lds(L, 1) <=
+                          (size_t)kLdsBudget;
+  return (path == Path::kWide && (tile != TK_TILE_AUTO || !small_wide)) ||
+         (path == Path::kRows && rows_ok);
 }
 
 template <typename TIn>
@@ -1196,7 +1202,7 @@ hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* 
                        hipStream_t st, bool f3 = false) {
   const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, (float*)out, L, B);
   // the BF16 row kernel reads four consecutive l per lane: L % 4 == 0, aligned
-  if (!bf16_kernel_applies(in, out, L, B, tile)) {
+  if (!bf16_kernel_applies(in, out, A, L, B, tile)) {
     if (out_bf16) return hipErrorInvalidValue;  // callers ask for BF16 output only here
     return launch_f32<TIn>(in, A, L, B, F, K, (float*)out, stream_in, tile, st);
   }
@@ -1310,18 +1316,18 @@ hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2
 // Largest L the TTM kernels accept (factor slice of at least one K-group in LDS).
 int ttm_max_L() { return (kLdsBudget - 4 * kTileLC * 256) / 16; }
 
-bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t L, int64_t B,
-                        const void* out, int tile) {
+bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t A, int64_t L,
+                        int64_t B, const void* out, int tile) {
   if (compute != TK_C_BF16) return false;
-  if (in_dtype == TK_F32) return bf16_kernel_applies((const float*)in, out, L, B, tile);
-  if (in_dtype == TK_BF16) return bf16_kernel_applies((const uint16_t*)in, out, L, B, tile);
+  if (in_dtype == TK_F32) return bf16_kernel_applies((const float*)in, out, A, L, B, tile);
+  if (in_dtype == TK_BF16) return bf16_kernel_applies((const uint16_t*)in, out, A, L, B, tile);
   return false;
 }
 
 hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
                       const void* F, int64_t K, void* out, hipStream_t st, bool stream_in,
                       int tile, int out_dtype) {
-  if (out_dtype == TK_BF16 && !ttm_bf16_output_ok(in_dtype, compute, in, L, B, out, tile))
+  if (out_dtype == TK_BF16 && !ttm_bf16_output_ok(in_dtype, compute, in, A, L, B, out, tile))
     return hipErrorInvalidValue;
   if (A * B == 0 || K == 0) return hipSuccess;
   if (compute == TK_C_FP64) {

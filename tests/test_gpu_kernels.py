@@ -76,9 +76,12 @@ def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
 
 
-def _bf16_mfma_path(L, B):
-    """Nodes the BF16 kernels take (others run the FP32 tile kernel)."""
-    return (B % 4 == 0 and B >= 16) or (B == 1 and L % 4 == 0)
+def _bf16_mfma_path(A, L, B):
+    """Nodes the BF16 kernels take: wide nodes whose 1024-column grid fills the
+    chip (256 blocks), and rows with L % 4 == 0.  Others run FP32 kernels (the
+    tile kernel, or the split-L wide kernel on small grids)."""
+    wide = B % 4 == 0 and B >= 16 and (A * B + 1023) // 1024 >= 256
+    return wide or (B == 1 and L % 4 == 0)
 
 
 # Reduced precision.  On the BF16 kernels every product of two bfloat16 values
@@ -90,7 +93,8 @@ BF16_BOUND = {"bf16": 1.5e-2, "bf16x3": 1e-4}
 
 
 @pytest.mark.parametrize("A,L,B,K", TTM_CASES + [(2, 64, 4096, 48), (4, 2048, 16, 5),
-                                                 (300, 400, 1, 44)])
+                                                 (300, 400, 1, 44), (512, 16, 512, 20),
+                                                 (3, 37, 100000, 5)])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 @pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
 def test_ttm_reduced_precision(A, L, B, K, storage, compute):
@@ -111,7 +115,7 @@ def test_ttm_reduced_precision(A, L, B, K, storage, compute):
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     exact = O.ttm(X64, F.astype(np.float64).T, 1)
-    if _bf16_mfma_path(L, B):
+    if _bf16_mfma_path(A, L, B):
         if compute == "bf16":
             model = P.ttm_bf16(X64, F.T, 1)
         else:
