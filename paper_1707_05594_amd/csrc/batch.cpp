@@ -453,7 +453,8 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
       if ((d.path == kGroupedRows &&
            (d.B != 1 || d.L % 4 != 0 || d.L > ttm_grouped_row_stage_max_L())) ||
           (d.path == kGroupedRowsDirect && (d.B != 1 || d.L % 4 != 0)) ||
-          (d.path == kGroupedRowsScalar && (d.B != 1 || d.L > ttm_grouped_row_stage_max_L())))
+          (d.path == kGroupedRowsScalar && (d.B != 1 || d.L > ttm_grouped_row_stage_max_L())) ||
+          (d.path == kGroupedWideScalar && d.B < 32))
         return bail(fail(TK_EINVAL, "internal: row body on an unsuitable node"));
   }
   if ((rc = upload(&b->ttm_nodes, nd_h, st)) || (rc = upload(&b->ttm_items, it_h, st)) ||

@@ -28,8 +28,9 @@ enum {
   kGroupedRows = 2,        // B == 1 through LDS, 16-byte loads (L % 4 == 0,
                            // L <= ttm_grouped_row_stage_max_L())
   kGroupedRowsDirect = 3,  // B == 1, direct 16-byte row loads (L % 4 == 0)
-  kGroupedRowsScalar = 4   // B == 1 through LDS, one element per load
+  kGroupedRowsScalar = 4,  // B == 1 through LDS, one element per load
                            // (L <= ttm_grouped_row_stage_max_L())
+  kGroupedWideScalar = 5   // B >= 32 not readable 16 bytes at a time: 4-byte loads
 };
 struct TtmNodeDesc {
   const void* in;

@@ -224,6 +224,100 @@ __global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
   wide_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
+// Wide variant with 4-byte loads, for runs of B (>= 32) that cannot be read
+// 16 bytes at a time (B % 4 != 0, or an unaligned base): lane i of wave w
+// owns the flattened columns c = 256 w + i + 64 j, j = 0..3, each with its
+// own (a, b); every load instruction reads 64 consecutive columns of one row
+// l (one run of B, or the end of one and the start of the next).
+constexpr int kWideScalarMinB = 32;
+
+template <int KG, typename TIn, bool NT>
+__device__ __forceinline__ void wide_scalar_body(const TIn* __restrict__ in,
+                                                 const float* __restrict__ F,
+                                                 float* __restrict__ out, int64_t C, int L,
+                                                 int64_t B, int Kt, int64_t blk, int k0,
+                                                 float* smem) {
+  stage_factor<KG>(smem, F, L, Kt, k0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c0 = (blk * 4 + wave) * 256;
+  if (c0 >= C) return;  // whole wave idle
+  const TIn* p[4];
+  int64_t q[4];
+  bool act[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = c0 + lane + 64 * j;
+    act[j] = c < C;
+    // columns past the end read column 0 (always in bounds) and store nothing
+    const int64_t a = act[j] ? c / B : 0;
+    const int64_t b = act[j] ? c - a * B : 0;
+    p[j] = in + (a * L) * B + b;
+    q[j] = (a * Kt) * B + b;
+  }
+  const float* ft = smem + (lane & 3) * L * KG;
+  f4 acc[KG][4];
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  constexpr int U = 8;
+  auto ld = [&](const TIn* a) -> float {
+    if constexpr (NT)
+      return Elem<TIn>::to_f32(__builtin_nontemporal_load(a));
+    else
+      return Elem<TIn>::to_f32(*a);
+  };
+  int l = 0;
+  for (; l + U <= L; l += U) {
+    float x[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) x[u][j] = ld(p[j] + (int64_t)(l + u) * B);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < KG; ++g) {
+        const float fa = ft[(l + u) * KG + g];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+      }
+  }
+  for (; l < L; ++l) {
+    float x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = ld(p[j] + (int64_t)l * B);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      const float fa = ft[l * KG + g];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[j], acc[g][j]);
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = k0 + 4 * g + m;
+      if (k < Kt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (act[j]) out[q[j] + (int64_t)k * B] = acc[g][j][m];
+    }
+}
+
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_wide_scalar_f32(const TIn* __restrict__ in,
+                                                           const float* __restrict__ F,
+                                                           float* __restrict__ out, int64_t C,
+                                                           int L, int64_t B, int Kt) {
+  extern __shared__ float smem[];
+  wide_scalar_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+}
+
 // Slab-aligned variant for runs of B (<= 256) that are not whole 128-byte
 // lines while every slab In[a, :, :] starts on a line: a wave takes
 // 64 / (B / 4) whole slabs, B / 4 lanes each (the rest idle), so no cache
@@ -867,6 +961,9 @@ __global__ __launch_bounds__(256, 3) void ttm_grouped(const TtmNodeDesc* __restr
     const TtmNodeDesc d = nodes[w.x];
     if (d.path == kGroupedWide)
       wide_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0, smem);
+    else if (d.path == kGroupedWideScalar)
+      wide_scalar_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0,
+                                   smem);
     else if (d.path == kGroupedRows)
       rows_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
     else if (d.path == kGroupedRowsScalar)
@@ -944,13 +1041,14 @@ namespace {
 
 constexpr int kLdsBudget = 64 * 1024;
 
-enum class Path { kWide, kWideSplitL, kRows, kTile };
+enum class Path { kWide, kWideSplitL, kWideScalar, kRows, kTile };
 
 template <typename TIn>
 Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
   const bool in_al = (uintptr_t)in % (4 * sizeof(TIn)) == 0;
   if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) return Path::kWide;
   if (B == 1) return Path::kRows;  // direct, or staged through LDS (short or unaligned rows)
+  if (B >= kWideScalarMinB) return Path::kWideScalar;
   return Path::kTile;
 }
 
@@ -960,6 +1058,7 @@ constexpr int kInst[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
 int64_t grid_blocks(Path path, int64_t A, int64_t B) {
   if (path == Path::kWide) return (A * B + 1023) / 1024;
   if (path == Path::kWideSplitL) return (A * B + 255) / 256;
+  if (path == Path::kWideScalar) return (A * B + 1023) / 1024;
   if (path == Path::kRows) return (A + 255) / 256;
   return 0;
 }
@@ -1039,6 +1138,11 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
       hipLaunchKernelGGL((ttm_wide_f32<KG, TIn, false>), grid, dim3(256), lds, st, in, F, out, C,
                          L, B, K);
     }
+  } else if (path == Path::kWideScalar) {
+    const int64_t C = A * B;
+    dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
+    hipLaunchKernelGGL((ttm_wide_scalar_f32<KG, TIn, NT>), grid, dim3(256), (size_t)16 * L * KG,
+                       st, in, F, out, C, L, B, K);
   } else if (path == Path::kWideSplitL) {
     if (KG > kSplitLMaxKG || splitl_lds(L, KG) > (size_t)kLdsBudget) return hipErrorInvalidValue;
     const int64_t C = A * B;
@@ -1276,6 +1380,9 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
     else
       d->path = L % 4 == 0 && in_al ? kGroupedRows : kGroupedRowsScalar;
     *tiles = (A + 255) / 256;
+  } else if (B >= kWideScalarMinB) {
+    d->path = kGroupedWideScalar;  // 1024 columns per item, 4-byte loads
+    *tiles = (A * B + 1023) / 1024;
   } else {
     d->path = kGroupedTile;
     *tiles = ((A + d->na - 1) / d->na) * d->nbt;

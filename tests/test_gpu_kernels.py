@@ -43,6 +43,8 @@ TTM_CASES = [
     (200, 200, 400, 20), # small wide grid: 313 blocks of 256 columns
     (13201, 32, 20, 6),  # slab-aligned wide path: 80-byte runs, 12 slabs per wave, ragged A
     (1320, 40, 200, 20), # slab-aligned wide path: one 800-byte-run slab per wave
+    (7, 50, 37, 12),     # 4-byte-load wide path: odd B, columns across a boundaries
+    (300, 30, 1001, 20), # 4-byte-load wide path on a full grid, ragged last wave
 ]
 
 
@@ -60,7 +62,7 @@ def test_ttm_fp32(A, L, B, K):
     assert rel_err(out.cpu().numpy(), ref) < 1e-5
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-11:])
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:])
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
