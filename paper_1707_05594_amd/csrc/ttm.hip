@@ -439,13 +439,16 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// 16-byte variant (L % 4 == 0, rows aligned for four-element loads): load
-// slot u of a lane covers four columns of row 8u + lane/8, so eight lanes read
-// 128 contiguous bytes of FP32 and every load instruction eight full segments.
-// The next chunk's loads are issued before the current chunk's MFMAs, and the
-// tile is private to the wave: after the factor is staged the waves of a
-// block never wait for each other.
-template <int KG, typename TIn, bool NT>
+// A wave reads its 64 rows chunk by chunk with every load instruction
+// covering whole row segments: V4 (L % 4 == 0, rows aligned for
+// four-element loads) -- load slot u of a lane is four columns of row
+// 8u + lane/8, so eight lanes read 128 contiguous bytes of FP32; otherwise
+// (odd L, or an unaligned base) one element per load -- slot u is column
+// lane % 32 of row 2u + lane/32, so 32 lanes read one row's 32 consecutive
+// elements.  The next chunk's loads are issued before the current chunk's
+// MFMAs, and the tile is private to the wave: after the factor is staged the
+// waves of a block never wait for each other.
+template <int KG, typename TIn, bool NT, bool V4 = true>
 __device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const float* __restrict__ F,
                                           float* __restrict__ out, int64_t A, int L, int Kt,
                                           int64_t blk, int k0, float* smem) {
@@ -458,31 +461,49 @@ __device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const floa
   const int nrows = (int)min((int64_t)64, A - row0);
   float* Xs = smem + 4 * L * KG + wave * 64 * kRowPitch;
   const float* ft = smem + (lane & 3) * L * KG;
-  const int rq = lane >> 3, cq = 4 * (lane & 7);
-  // slots past the wave's last row re-read that row
-  const TIn* rp[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) rp[u] = in + (row0 + min(8 * u + rq, nrows - 1)) * (int64_t)L;
+  const TIn* base = in + row0 * (int64_t)L;
 
   f4 acc[KG];
 #pragma unroll
   for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
 
-  f4 v[8];
-  // in a short last chunk, lanes past its end re-read its last four columns
+  // slots past the wave's last row re-read that row; in a short last chunk,
+  // lanes past its end re-read its last columns
+  constexpr int kSlots = V4 ? 8 : 32;
+  using Slot = typename std::conditional<V4, f4, float>::type;
+  Slot v[kSlots];
+  const int rq = V4 ? lane >> 3 : lane >> 5;                  // row within a slot's group
+  const int cq = V4 ? 4 * (lane & 7) : lane & (kRowLC - 1);   // first column
+  constexpr int kRowStep = V4 ? 8 : 2;                        // rows between slots
   auto load_chunk = [&](int l0) {
-    const int c = l0 + min(cq, min(kRowLC, L - l0) - 4);
+    const int lc = min(kRowLC, L - l0);
+    const int c = l0 + min(cq, lc - (V4 ? 4 : 1));
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = load4_f32<NT>(rp[u] + c);
+    for (int u = 0; u < kSlots; ++u) {
+      const TIn* pr = base + (int64_t)min(kRowStep * u + rq, nrows - 1) * L + c;
+      if constexpr (V4) {
+        v[u] = load4_f32<NT>(pr);
+      } else if constexpr (NT) {
+        v[u] = Elem<TIn>::to_f32(__builtin_nontemporal_load(pr));
+      } else {
+        v[u] = Elem<TIn>::to_f32(*pr);
+      }
+    }
   };
   load_chunk(0);
   const float* xr = Xs + lane * kRowPitch;
   for (int l0 = 0; l0 < L; l0 += kRowLC) {
     wave_lds_fence();  // the previous chunk's reads are issued before these writes
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < kSlots; ++u) {
+      float* xs = Xs + (kRowStep * u + rq) * kRowPitch + cq;
+      if constexpr (V4) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) Xs[(8 * u + rq) * kRowPitch + cq + j] = v[u][j];
+        for (int j = 0; j < 4; ++j) xs[j] = v[u][j];
+      } else {
+        xs[0] = v[u];
+      }
+    }
     wave_lds_fence();
     if (l0 + kRowLC < L) load_chunk(l0 + kRowLC);
     if (L - l0 >= kRowLC) {
@@ -513,19 +534,19 @@ __device__ __forceinline__ void rows_body(const TIn* __restrict__ in, const floa
   }
 }
 
-template <int KG, typename TIn, bool NT>
+template <int KG, typename TIn, bool NT, bool V4>
 __global__ __launch_bounds__(256) void ttm_rows_f32(const TIn* __restrict__ in,
                                                     const float* __restrict__ F,
                                                     float* __restrict__ out, int64_t A, int L,
                                                     int Kt) {
   extern __shared__ float smem[];
-  rows_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
+  rows_body<KG, TIn, NT, V4>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
-// Single-element variant, for rows that cannot be read 16 bytes at a time
-// (odd L, or an unaligned base): one element per load, 32 in flight, eight
-// rows' 32 consecutive elements per load instruction; block barriers around
-// each chunk.
+// Single-element row body with block barriers around each chunk (one element
+// per load, eight rows' 32 consecutive elements per load instruction), kept
+// for the grouped kernel: there the barrier-free body above measured slower
+// (the persistent kernel's register budget is shared by all bodies).
 template <int KG, typename TIn, bool NT>
 __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
                                               const float* __restrict__ F,
@@ -576,15 +597,6 @@ __device__ __forceinline__ void rows_lds_body(const TIn* __restrict__ in,
       const int k = k0 + 4 * g + m;
       if (k < Kt) q[k] = acc[g][m];
     }
-}
-
-template <int KG, typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_rows_lds_f32(const TIn* __restrict__ in,
-                                                        const float* __restrict__ F,
-                                                        float* __restrict__ out, int64_t A, int L,
-                                                        int Kt) {
-  extern __shared__ float smem[];
-  rows_lds_body<KG, TIn, NT>(in, F, out, A, L, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
 // ------------------------------------------------------------- BF16 MFMA paths --
@@ -1152,18 +1164,24 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
   } else if (path == Path::kRows) {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
     const size_t staged = (size_t)16 * L * KG + kRowStageBytes;
+    // rows that are not whole 128-byte lines share a line with the next
+    // column chunk: normal loads keep it cached until then
+    const bool nt = NT && (L * sizeof(TIn)) % 128 == 0;
     if (!rows_v4(in, L)) {
-      hipLaunchKernelGGL((ttm_rows_lds_f32<KG, TIn, NT>), grid, dim3(256), staged, st, in, F,
-                         out, A, L, K);
-    } else if (staged <= (size_t)kLdsBudget) {
-      // rows that are not whole 128-byte lines share a line with the next
-      // column chunk: normal loads keep it cached until then
-      if (NT && (L * sizeof(TIn)) % 128 == 0)
-        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, true>), grid, dim3(256), staged, st, in, F,
-                           out, A, L, K);
+      if (staged > (size_t)kLdsBudget) return hipErrorInvalidValue;  // launch_f32 prevents it
+      if (nt)
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, true, false>), grid, dim3(256), staged, st, in,
+                           F, out, A, L, K);
       else
-        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, false>), grid, dim3(256), staged, st, in, F,
-                           out, A, L, K);
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, false, false>), grid, dim3(256), staged, st, in,
+                           F, out, A, L, K);
+    } else if (staged <= (size_t)kLdsBudget) {
+      if (nt)
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, true, true>), grid, dim3(256), staged, st, in,
+                           F, out, A, L, K);
+      else
+        hipLaunchKernelGGL((ttm_rows_f32<KG, TIn, false, true>), grid, dim3(256), staged, st, in,
+                           F, out, A, L, K);
     } else {  // the factor slice leaves no room for the row tiles
       const size_t lds = (size_t)16 * L * KG;
       hipLaunchKernelGGL((ttm_rows_direct_f32<KG, TIn, NT>), grid, dim3(256), lds, st, in, F,
