@@ -63,9 +63,12 @@ extern "C" {
 #define TK_C_BF16X3 3 /* split BF16: a*b ~ ah*bh + ah*bl + al*bh, FP32 accumulation */
 
 /* TTM kernel choice for one node (FP32 / BF16 / bf16x3 compute):
- * AUTO   -- by shape: the wide path (B % 4 == 0, B >= 16), the row path
- *           (B == 1, L % 4 == 0), else the LDS-staged tile path; the K-group
- *           count from the factor's LDS footprint and the grid size;
+ * AUTO   -- by shape: the wide path (B % 4 == 0, B >= 16; split over L on
+ *           grids smaller than the chip; whole slabs per wave for FP32 runs
+ *           that are not whole cache lines), the wide path with 4-byte loads
+ *           (B >= 32 otherwise), the row path (B == 1), else the LDS-staged
+ *           tile path; the K-group count from the factor's LDS footprint and
+ *           the grid size;
  * STAGED -- always the LDS-staged tile path;
  * SPLITK -- AUTO's path with half the K-groups per block (more blocks, the
  *           input re-read from cache). */
