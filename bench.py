@@ -16,7 +16,7 @@ Prints ONE JSON line.  Extra objects:
   cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
                   host for a bounded sample: one HOOI invocation of the same
                   tensor.
-  c3_bf16_storage -- the 80^5 rank-10 tensor stored as BF16, HOOI with FP32,
+  bf16_storage_80x80x80x80x80 -- the 80^5 rank-10 tensor stored as BF16, HOOI with FP32,
                   bf16x3 and BF16 TTMs (precision study), FP64 residual errors.
   batch        -- batched HOOI over 512 planted 3- and 4-mode tensors (grouped
                   persistent TTM levels in a replayed HIP graph).
@@ -46,7 +46,7 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "ttm_wide_f32_root_c2_hbm_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "ttm_wide_f32_root_200x200x200x200_r20_hbm_counters.txt")
 
 
 def recorded_traffic():
@@ -126,7 +126,7 @@ def cpu_baseline(T32, K, F0, min_seconds=10.0, max_invocations=30):
                 seconds=round(dt, 2))
 
 
-def c3_leg(steps, warmup):
+def five_mode_bf16_leg(steps, warmup):
     """The five-mode 80^5 tensor stored as BF16 (rank 10, 1e-2 relative noise):
     HOOI iterations/s with FP32, bf16x3 and BF16 TTMs, each run's error by the
     FP64 explicit residual against the stored tensor."""
@@ -141,7 +141,7 @@ def c3_leg(steps, warmup):
     Td = torch.from_numpy(T.view("int16")).view(torch.bfloat16).to(dev)
     del T
     torch.cuda.synchronize()
-    log(f"c3: generated 80^5 BF16 in {time.perf_counter() - t0:.1f}s")
+    log(f"80^5: generated 80^5 BF16 in {time.perf_counter() - t0:.1f}s")
     plan = tk.ttm_tree_plan(info["L"], K)
     res = {"workload": "planted 80x80x80x80x80 stored BF16, Tucker rank 10/mode, 1e-2 rel noise, "
                        "HOSVD start, DP-optimal TTM-tree", "tree": plan.string(),
@@ -161,7 +161,7 @@ def c3_leg(steps, warmup):
         res[compute] = {"value": round(1.0 / dt, 3), "unit": "HOOI iters/s",
                         "ms_per_step": round(1e3 * dt, 4), "rel_err": errs[-1],
                         "rel_err_explicit": ctx.error_explicit()}
-        log(f"c3 {compute}: {res[compute]['value']} it/s, error {res[compute]['rel_err_explicit']:.6e}")
+        log(f"80^5 {compute}: {res[compute]['value']} it/s, error {res[compute]['rel_err_explicit']:.6e}")
         del ctx
     del Td
     torch.cuda.empty_cache()
@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
-    ap.add_argument("--skip-c3", action="store_true")
+    ap.add_argument("--skip-five-mode", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
                          "(reference dispatches for HBM counter calibration)")
@@ -353,8 +353,8 @@ def main():
         out["mixed"] = mixed
         del Tb
 
-    if not args.skip_c3:
-        out["c3_bf16_storage"] = c3_leg(args.steps, args.warmup)
+    if not args.skip_five_mode:
+        out["bf16_storage_80x80x80x80x80"] = five_mode_bf16_leg(args.steps, args.warmup)
 
     if not args.skip_batch:
         out["batch"] = batch_leg(args.steps, args.warmup)

@@ -35,7 +35,7 @@ def _leaf_at(leaf, idx):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def planted_200x4():
     torch, dev = torch_dev()
     print("generating planted 200^4 rank-20 FP32", flush=True)
     T, info = synth.workload("planted_200x200x200x200_r20_f32")
@@ -44,8 +44,8 @@ def c2():
     return T, info, Td
 
 
-def test_c2_sampled_leaves_and_gram_invariant(c2):
-    T, info, Td = c2
+def test_200x4_sampled_leaves_and_gram_invariant(planted_200x4):
+    T, info, Td = planted_200x4
     L, K = info["L"], info["K"]
     print("200^4: HOSVD start, one tree pass", flush=True)
     ctx = tk.hooi_init(Td, K, compute="fp32", plan=tk.ttm_tree_plan(L, K))
@@ -73,8 +73,8 @@ def test_c2_sampled_leaves_and_gram_invariant(c2):
     assert np.ptp(traces) < 1e-5 * traces.max()
 
 
-def test_c2_iterations_properties(c2):
-    T, info, Td = c2
+def test_200x4_iterations_properties(planted_200x4):
+    T, info, Td = planted_200x4
     L, K = info["L"], info["K"]
     print("200^4: HOSVD + 3 HOOI invocations", flush=True)
     ctx = tk.hooi_init(Td, K, compute="fp32")
@@ -100,7 +100,7 @@ def test_c2_iterations_properties(c2):
 
 
 @pytest.fixture(scope="module")
-def c3():
+def planted_80x5_bf16():
     torch, dev = torch_dev()
     print("generating planted 80^5 rank-10 BF16", flush=True)
     T, info = synth.workload("planted_80x80x80x80x80_r10_bf16")
@@ -112,8 +112,8 @@ def c3():
 
 
 @pytest.mark.parametrize("compute,bound", [("bf16x3", 1e-4), ("bf16", 1.5e-2)])
-def test_c3_bf16_storage_sampled_leaves(c3, compute, bound):
-    T32, info, Td = c3
+def test_80x5_bf16_storage_sampled_leaves(planted_80x5_bf16, compute, bound):
+    T32, info, Td = planted_80x5_bf16
     L, K = info["L"], info["K"]
     print(f"80^5 BF16 storage, {compute}: one tree pass", flush=True)
     ctx = tk.hooi_init(Td, K, compute=compute)
