@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256, sizeof(TIn) == 8 ? 2 : 4) void gram_grouped_pa
 // sums are added in group order (a fixed order for a given shape).
 constexpr int kRG = 8, kRE = 32;
 
-__device__ __forceinline__ double gram_chunk_sum(const double* __restrict__ part, int L, int T,
+__device__ __forceinline__ double gram_chunk_sum(const double* __restrict__ part, int T,
                                                  int npairs, int nchunks, int i, int j, int g) {
   int ii = i, jj = j;
   if (ii / kGT > jj / kGT) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ pa
   const int g = threadIdx.x / kRE, q = threadIdx.x % kRE;
   const int64_t e = (int64_t)blockIdx.x * kRE + q;
   const bool ok = e < (int64_t)L * L;
-  const double s = ok ? gram_chunk_sum(part, L, T, npairs, nchunks, (int)(e / L), (int)(e % L), g)
+  const double s = ok ? gram_chunk_sum(part, T, npairs, nchunks, (int)(e / L), (int)(e % L), g)
                       : 0.0;
   const double t = combine_groups(s, red);
   if (g == 0 && ok) S[e] = t;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void gram_grouped_reduce(const GramDesc* __res
     }
     const GramDesc d = mats[lo];
     rel = e - elem_off[lo];
-    s = gram_chunk_sum(d.part, d.L, d.T, d.npairs, d.nchunks, (int)(rel / d.L),
+    s = gram_chunk_sum(d.part, d.T, d.npairs, d.nchunks, (int)(rel / d.L),
                        (int)(rel % d.L), g);
   }
   const double t = combine_groups(s, red);

@@ -1056,7 +1056,7 @@ constexpr int kLdsBudget = 64 * 1024;
 enum class Path { kWide, kWideSplitL, kWideScalar, kRows, kTile };
 
 template <typename TIn>
-Path choose_path(const TIn* in, const float* out, int64_t L, int64_t B) {
+Path choose_path(const TIn* in, const float* out, int64_t B) {
   const bool in_al = (uintptr_t)in % (4 * sizeof(TIn)) == 0;
   if (B % 4 == 0 && B >= 16 && in_al && (uintptr_t)out % 16 == 0) return Path::kWide;
   if (B == 1) return Path::kRows;  // direct, or staged through LDS (short or unaligned rows)
@@ -1229,7 +1229,7 @@ template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                       float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
-  Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, L, B);
+  Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, B);
   // LDS beside the factor slice: the staged tile, or the row tiles when one
   // K-group fits beside them (else 16-byte rows are read directly, and
   // single-element rows take the tile path)
@@ -1310,7 +1310,7 @@ template <typename TIn>
 bool bf16_kernel_applies(const TIn* in, const void* out, int64_t A, int64_t L, int64_t B,
                          int tile) {
   if (tile == TK_TILE_STAGED) return false;
-  const Path path = choose_path(in, (const float*)out, L, B);
+  const Path path = choose_path(in, (const float*)out, B);
   const bool rows_ok = L % 4 == 0 && (uintptr_t)in % (4 * sizeof(TIn)) == 0;
   const bool small_wide = grid_blocks(Path::kWide, A, B) < 256 && splitl_lds(L, 1) <=
                           (size_t)kLdsBudget;
@@ -1322,7 +1322,7 @@ template <typename TIn>
 hipError_t launch_bf16(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                        void* out, bool stream_in, bool x3, bool out_bf16, int tile,
                        hipStream_t st, bool f3 = false) {
-  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, (float*)out, L, B);
+  const Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, (float*)out, B);
   // the BF16 row kernel reads four consecutive l per lane: L % 4 == 0, aligned
   if (!bf16_kernel_applies(in, out, A, L, B, tile)) {
     if (out_bf16) return hipErrorInvalidValue;  // callers ask for BF16 output only here
@@ -1484,7 +1484,7 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   // bfloat16 pairs are exact in FP32, so this matches an FP32 MFMA chain up
   // to the order of the FP32 accumulation); otherwise the FP32 kernels
   const uint16_t* in16 = (const uint16_t*)in;
-  if (tile == TK_TILE_AUTO && choose_path(in16, (const float*)out, L, B) == Path::kWide &&
+  if (tile == TK_TILE_AUTO && choose_path(in16, (const float*)out, B) == Path::kWide &&
       grid_blocks(Path::kWide, A, B) >= 256)
     return launch_bf16<uint16_t>(in16, A, (int)L, B, (const float*)F, (int)K, out, stream_in,
                                  true, false, tile, st, true);
