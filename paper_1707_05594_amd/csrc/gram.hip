@@ -254,33 +254,51 @@ __global__ __launch_bounds__(256) void gram_reduce(const double* __restrict__ pa
 }
 
 // Element e of the concatenated L_m x L_m results of all matrices: matrix m
-// with elem_off[m] <= e < elem_off[m + 1] (binary search), then as gram_reduce.
+// with elem_off[m] <= e < elem_off[m + 1] (binary search), one thread per
+// element.  The thread adds the chunks in gram_reduce's order (group g's chunks
+// g, g + kRG, ... in order, then the kRG group sums in group order), so both
+// reductions give the same bits for the same partials.
 __global__ __launch_bounds__(256) void gram_grouped_reduce(const GramDesc* __restrict__ mats,
                                                            const int64_t* __restrict__ elem_off,
                                                            int n_mats) {
-  __shared__ double red[kRG][kRE];
-  const int g = threadIdx.x / kRE, q = threadIdx.x % kRE;
-  const int64_t e = (int64_t)blockIdx.x * kRE + q;
-  const bool ok = e < elem_off[n_mats];
-  double s = 0.0;
-  int lo = 0;
-  int64_t rel = 0;
-  if (ok) {
-    int hi = n_mats - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) / 2;
-      if (elem_off[mid] <= e)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const GramDesc d = mats[lo];
-    rel = e - elem_off[lo];
-    s = gram_chunk_sum(d.part, d.T, d.npairs, d.nchunks, (int)(rel / d.L),
-                       (int)(rel % d.L), g);
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= elem_off[n_mats]) return;
+  int lo = 0, hi = n_mats - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (elem_off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
   }
-  const double t = combine_groups(s, red);
-  if (g == 0 && ok) mats[lo].S[rel] = t;
+  const GramDesc d = mats[lo];
+  const int64_t rel = e - elem_off[lo];
+  int ii = (int)(rel / d.L), jj = (int)(rel % d.L);
+  if (ii / kGT > jj / kGT) {
+    const int t = ii;
+    ii = jj;
+    jj = t;
+  }
+  const int ti = ii / kGT, tj = jj / kGT;
+  const int p = ti * d.T - ti * (ti - 1) / 2 + (tj - ti);
+  const double* src = d.part + (int64_t)p * (kGT * kGT) + (ii - ti * kGT) * kGT + (jj - tj * kGT);
+  const int64_t stride = (int64_t)d.npairs * (kGT * kGT);
+  double t = 0.0;
+  if (d.nchunks <= kRG) {
+    // one chunk per group: the group sums are the chunks themselves
+    double v[kRG];
+#pragma unroll
+    for (int g = 0; g < kRG; ++g) v[g] = g < d.nchunks ? src[g * stride] : 0.0;
+#pragma unroll
+    for (int g = 0; g < kRG; ++g) t += v[g];
+  } else {
+    for (int g = 0; g < kRG; ++g) {
+      double s = 0.0;
+      for (int ch = g; ch < d.nchunks; ch += kRG) s += src[ch * stride];
+      t += s;
+    }
+  }
+  d.S[rel] = t;
 }
 
 namespace {
@@ -332,7 +350,7 @@ hipError_t launch_gram_grouped(int in_dtype, const GramDesc* mats, const int4* i
                        items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gram_grouped_reduce, dim3((unsigned)((total_elems + kRE - 1) / kRE)),
+  hipLaunchKernelGGL(gram_grouped_reduce, dim3((unsigned)((total_elems + 255) / 256)),
                      dim3(256), 0, st, mats, elem_off, n_mats);
   return hipGetLastError();
 }
