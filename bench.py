@@ -14,8 +14,8 @@ Prints ONE JSON line.  Extra objects:
                   counter summary under profiles/ (null once the kernel
                   sources differ from those the counters were taken with).
   cpu_baseline -- the FP64 oracle (naive per-mode chains, NumPy) timed on the
-                  host for a bounded sample: one HOOI invocation of the same
-                  tensor.
+                  host for a bounded sample: consecutive HOOI invocations of
+                  the same tensor until at least 10 s of CPU work.
   bf16_storage_80x80x80x80x80 -- the 80^5 rank-10 tensor stored as BF16, HOOI with FP32,
                   bf16x3 and BF16 TTMs (precision study), FP64 residual errors.
   batch        -- batched HOOI over 512 planted 3- and 4-mode tensors (grouped
@@ -255,11 +255,11 @@ def main():
     ap.add_argument("--skip-five-mode", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
-                         "(reference dispatches for HBM counter calibration)")
+                         "(dispatches of known size that calibrate the HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md only)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
