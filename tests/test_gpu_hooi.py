@@ -1,14 +1,17 @@
 """End-to-end HOOI on the GPU through the C ABI against the FP64 oracle.
 
-Bars (from the arithmetic): FP64 leaves/errors within 1e-10 relative; FP32
-leaves within 1e-5; factors compared basis-free (projector distance) and, where
-the planted eigen-gap makes them unique, element-wise after the sign rule."""
+Bars (from the arithmetic): leaves element-wise within the first-order bound
+of their chain of TTMs relative to the chain over |T| and |F| (tests/gpu_util.py
+states the per-precision bounds); FP64 errors within 1e-10 relative; factors
+compared basis-free (projector distance) and, where the planted eigen-gap makes
+them unique, element-wise after the sign rule."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import hooi as O
-from tests.gpu_util import rel_err, subspace_dist, to_dev, torch_dev
+from tests.gpu_util import (abs_chain, assert_elementwise, chain_tol, rel_err, subspace_dist,
+                            to_dev, torch_dev)
 
 pytestmark = pytest.mark.gpu
 tk = pytest.importorskip("paper_1707_05594_amd")
@@ -60,7 +63,7 @@ def test_naive_chain_and_dp_tree_agree():
 
 
 CASES = [
-    # (L, K, storage, compute, tol)
+    # (L, K, storage, compute, normwise bar reported beside the element-wise check)
     ((64, 64, 64), (8, 8, 8), "f64", "fp64", 1e-10),
     ((24, 20, 16, 12), (4, 5, 3, 6), "f32", "fp32", 1e-5),
     ((30, 7, 9, 5), (3, 2, 4, 2), "f32", "fp32", 1e-5),
@@ -97,9 +100,18 @@ def test_tree_leaves_equal_naive_chain(L, K, dtype, compute, tol, kind):
     g2 = float(np.sum(core * core))
     for n in range(len(L)):
         Y = O.chain_except(T64, F, n)
-        assert rel_err(ctx.leaf(n), Y) < tol, n
+        Ya = abs_chain(T64, F, n)
+        etol = chain_tol([L[j] for j in range(len(L)) if j != n], compute,
+                         bf16_input=dtype == "bf16")
+        if compute == "fp64":
+            etol *= 2  # the oracle rounds in FP64 too
+        leaf = ctx.leaf(n)
+        assert_elementwise(leaf, Y, Ya, etol, f"leaf {n} {kind} {dtype}/{compute}")
+        assert rel_err(leaf, Y) < tol, n
         S = ctx.gram(n)
-        assert rel_err(S, O.gram(Y, n)) < 2 * tol
+        C = Y.size // L[n]
+        assert_elementwise(S, O.gram(Y, n), O.gram(Ya, n), 2 * etol + 2 * (C + 2) * 2.0 ** -53,
+                           f"gram {n} {kind} {dtype}/{compute}")
         # ||G||^2 = trace(F_n^T S_n F_n) for every n
         assert abs(np.trace(F[n].T @ S @ F[n]) - g2) < 4 * tol * g2
 

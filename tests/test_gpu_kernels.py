@@ -1,16 +1,21 @@
 """Kernel-level parity on the GPU: TTM node, Gram and FP64 eigensolver against
 the FP64 oracle, called through the C ABI.
 
-Tolerances: FP64 results within 1e-10 normwise relative; FP32 results within
-1e-5 (FP32 rounding of an L-term dot product is about sqrt(L) * 6e-8 relative);
-Gram from FP32/BF16 inputs is formed from exact FP64 products, so 1e-12."""
+Every comparison is element-wise against the oracle's contraction of the
+absolute values (tests/gpu_util.py states the bounds): a TTM with reduction
+length L is within (L + 2) u of that magnitude bound (u = 2^-24 for FP32,
+2^-53 for FP64; 3 L + 2 for FP32 compute on BF16 input, which sums three exact
+products per term), and the reduced-precision modes add their operand
+rounding.  The Gram from FP32/BF16 inputs is formed from exact FP64 products,
+so its bound is (C + 2) 2^-53 for C columns."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import hooi as O
 from oracle import precision as P
-from tests.gpu_util import rel_err, subspace_dist, to_dev, torch_dev
+from tests.gpu_util import (abs_gram, abs_ttm, assert_elementwise, subspace_dist,
+                            to_dev, torch_dev, ttm_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +63,10 @@ def test_ttm_fp32(A, L, B, K):
     out = torch.full((A, K, B), float("nan"), dtype=torch.float32, device=dev)
     tk.ttm(to_dev(X), A, L, B, to_dev(F), K, out)
     torch.cuda.synchronize()
-    ref = O.ttm(X.astype(np.float64), F.astype(np.float64).T, 1)
-    assert rel_err(out.cpu().numpy(), ref) < 1e-5
+    X64, F64 = X.astype(np.float64), F.astype(np.float64)
+    ref = O.ttm(X64, F64.T, 1)
+    assert_elementwise(out.cpu().numpy(), ref, abs_ttm(X64, F64.T, 1), ttm_tol(L, "fp32"),
+                       f"ttm fp32 {A}x{L}x{B} K={K}")
 
 
 @pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:])
@@ -74,8 +81,10 @@ def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     out = torch.empty((A, K, B), dtype=torch.float32, device=dev)
     tk.ttm(xt, A, L, B, to_dev(F), K, out)
     torch.cuda.synchronize()
-    ref = O.ttm(O.as_f64(Xb, "bf16"), F.astype(np.float64).T, 1)
-    assert rel_err(out.cpu().numpy(), ref) < 1e-5
+    X64, F64 = O.as_f64(Xb, "bf16"), F.astype(np.float64)
+    ref = O.ttm(X64, F64.T, 1)
+    assert_elementwise(out.cpu().numpy(), ref, abs_ttm(X64, F64.T, 1),
+                       ttm_tol(L, "fp32", bf16_input=True), f"ttm bf16->fp32 {A}x{L}x{B} K={K}")
 
 
 def _bf16_mfma_path(A, L, B):
@@ -88,10 +97,11 @@ def _bf16_mfma_path(A, L, B):
 
 # Reduced precision.  On the BF16 kernels every product of two bfloat16 values
 # is exact in FP32, so the result equals the float64 model of the mode
-# (oracle.precision) up to FP32 accumulation: 1e-5.  Against the exact
-# product the stated bounds are 1.5e-2 (BF16: one rounding of each operand,
-# 2^-8 relative) and 1e-4 (bf16x3: 2^-16 representation error per operand).
-BF16_BOUND = {"bf16": 1.5e-2, "bf16x3": 1e-4}
+# (oracle.precision) up to FP32 accumulation of L (BF16) or 3 L (bf16x3)
+# exact products.  Against the exact product the per-element bounds add the
+# operand rounding: 2^-7 + 2^-16 for BF16 (one rounding of each operand,
+# 2^-8 relative), 4 * 2^-16 for bf16x3 (2^-16 representation error per
+# operand plus the dropped lo * lo product).
 
 
 @pytest.mark.parametrize("A,L,B,K", TTM_CASES + [(2, 64, 4096, 48), (4, 2048, 16, 5),
@@ -116,16 +126,23 @@ def test_ttm_reduced_precision(A, L, B, K, storage, compute):
     tk.ttm(xt, A, L, B, to_dev(F), K, out, compute=compute)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
-    exact = O.ttm(X64, F.astype(np.float64).T, 1)
+    F64 = F.astype(np.float64)
+    exact = O.ttm(X64, F64.T, 1)
+    mag = abs_ttm(X64, F64.T, 1)
+    tag = f"ttm {storage}/{compute} {A}x{L}x{B} K={K}"
     if _bf16_mfma_path(A, L, B):
         if compute == "bf16":
             model = P.ttm_bf16(X64, F.T, 1)
+            tol = ttm_tol(L, "fp32")
         else:
             model = P.ttm_bf16x3(X64, F.T, 1, x_is_bf16=storage == "bf16")
-        assert rel_err(got, model) < 1e-5
+            tol = ttm_tol(L, "fp32", bf16_input=True)
+        # model terms are products of operands within 2^-8 of the exact ones
+        assert_elementwise(got, model, mag, tol * (1 + 2.0 ** -6), tag + " vs model")
     else:
-        assert rel_err(got, exact) < 1e-5
-    assert rel_err(got, exact) < BF16_BOUND[compute]
+        assert_elementwise(got, exact, mag, ttm_tol(L, "fp32", bf16_input=storage == "bf16"),
+                           tag + " (FP32 kernel)")
+    assert_elementwise(got, exact, mag, ttm_tol(L, compute), tag + " vs exact")
 
 
 @pytest.mark.parametrize("A,L,B,K", [(3, 37, 100, 5), (100, 64, 1, 8), (7, 20, 9, 20),
@@ -139,7 +156,9 @@ def test_ttm_fp64(A, L, B, K):
     out = torch.empty((A, K, B), dtype=torch.float64, device=dev)
     tk.ttm(to_dev(X), A, L, B, to_dev(F), K, out, compute="fp64")
     torch.cuda.synchronize()
-    assert rel_err(out.cpu().numpy(), O.ttm(X, F.T, 1)) < 1e-13
+    # both sides round in FP64: twice the bound of one
+    assert_elementwise(out.cpu().numpy(), O.ttm(X, F.T, 1), abs_ttm(X, F.T, 1),
+                       2 * ttm_tol(L, "fp64"), f"ttm fp64 {A}x{L}x{B} K={K}")
 
 
 def test_ttm_identity_factor_copies_input():
@@ -180,7 +199,9 @@ def test_gram(A, L, B, dtype):
     tk.gram(Yd, A, L, B, S)
     torch.cuda.synchronize()
     Sh = S.cpu().numpy()
-    assert rel_err(Sh, O.gram(Y64, 1)) < 1e-12
+    # both sides round in FP64: twice the bound of one
+    assert_elementwise(Sh, O.gram(Y64, 1), abs_gram(Y64, 1), 2 * (A * B + 2) * 2.0 ** -53,
+                       f"gram {A}x{L}x{B} {dtype}")
     np.testing.assert_array_equal(Sh, Sh.T)
     # deterministic: a second run gives identical bits
     S2 = torch.empty_like(S)
