@@ -112,6 +112,32 @@ def hosvd(T: np.ndarray, K) -> list:
     return [lead(T, n, int(K[n]))[0] for n in range(T.ndim)]
 
 
+def sthosvd(T: np.ndarray, K, order=None):
+    """Sequentially truncated HOSVD, the initial decomposition of Sec. 1 and
+    Sec. 2.2: modes are processed one after another (ascending unless `order`
+    is given); mode n takes the leading K_n left singular vectors of the
+    current tensor's mode-n unfolding and truncates the tensor along n
+    before the next mode.  Returns (F, G, discarded) with G the truncated
+    tensor (the core) and discarded[i] the sum of the eigenvalues of the
+    i-th step's Gram beyond the K_n leading ones (the energy that step
+    removes)."""
+    N = T.ndim
+    order = list(range(N)) if order is None else [int(n) for n in order]
+    if sorted(order) != list(range(N)):
+        raise ValueError(f"order {order} is not a permutation of the modes")
+    F = [None] * N
+    Y = np.asarray(T, dtype=np.float64)
+    discarded = []
+    for n in order:
+        S = gram(Y, n)
+        w = np.linalg.eigvalsh(S)
+        Fn, wn = leading_eigvecs(S, int(K[n]))
+        discarded.append(float(np.sum(w) - np.sum(wn)))
+        F[n] = Fn
+        Y = ttm(Y, Fn.T, n)
+    return F, Y, discarded
+
+
 def new_core(T: np.ndarray, F) -> np.ndarray:
     """G = T x_1 F_1^T x_2 ... x_N F_N^T (Fig. 2, new core)."""
     G = T

@@ -196,3 +196,61 @@ def test_bf16_upcast_exact():
     bits = np.array([0x3F80, 0xC000, 0x0000, 0x3E80, 0x7F7F], dtype=np.uint16)
     np.testing.assert_array_equal(O.as_f64(bits, "bf16"),
                                   [1.0, -2.0, 0.0, 0.25, float(np.float32(3.3895314e38))])
+
+
+# ---------------------------------------------------------------------------
+# STHOSVD (initial decomposition, Sec. 1 and Sec. 2.2)
+# ---------------------------------------------------------------------------
+def test_sthosvd_two_modes_equals_truncated_svd():
+    """N = 2: the first step is the leading K left singular vectors of T, the
+    second the leading K right singular vectors of U_K^T T = Sigma_K V_K^T:
+    both factors span the truncated SVD's subspaces, and the error is the
+    Eckart-Young tail sqrt(sum_{i>K} sigma_i^2) / ||T||."""
+    g = np.random.default_rng(4)
+    T = g.standard_normal((30, 22))
+    K = (5, 5)
+    F, G, disc = O.sthosvd(T, K)
+    U, sv, Vt = np.linalg.svd(T)
+    assert np.linalg.norm(F[0] @ F[0].T - U[:, :5] @ U[:, :5].T, 2) < 1e-12
+    assert np.linalg.norm(F[1] @ F[1].T - Vt[:5].T @ Vt[:5], 2) < 1e-12
+    e = O.rel_error_explicit(T, G, F)
+    assert abs(e - np.sqrt(np.sum(sv[5:] ** 2)) / np.linalg.norm(T)) < 1e-12
+    # the second step discards nothing: U_K^T T has rank K
+    assert abs(disc[1]) < 1e-10 * np.sum(sv ** 2)
+
+
+def test_sthosvd_recovers_planted_tensor():
+    L, K = (14, 12, 10, 9), (3, 4, 2, 3)
+    T, info = synth.planted(L, K, noise=0.0, dtype="f64", cfg=90)
+    for order in (None, (3, 1, 0, 2)):
+        F, G, disc = O.sthosvd(T, K, order=order)
+        for n in range(4):
+            U = info["factors"][n]
+            assert np.linalg.norm(F[n] @ F[n].T - U @ U.T, 2) < 1e-10
+        assert O.rel_error_explicit(T, G, F) < 1e-13
+
+
+def test_sthosvd_error_is_sum_of_discarded_energy():
+    """The residual of STHOSVD splits into the parts each step removes, and
+    they are mutually orthogonal: ||T - G x F||^2 = sum of the discarded
+    eigenvalue tails of the sequential Grams (exact, any order); each tail is
+    at most the tail of the original unfolding, so the error is at most the
+    HOSVD bound sqrt(sum_n tail_n(T_(n)))."""
+    g = np.random.default_rng(12)
+    T = g.standard_normal((11, 9, 8, 7))
+    K = (4, 3, 5, 2)
+    nT2 = float(np.sum(T * T))
+    for order in (None, (2, 0, 3, 1)):
+        F, G, disc = O.sthosvd(T, K, order=order)
+        e = O.rel_error_explicit(T, G, F)
+        assert abs(e * e * nT2 - sum(disc)) < 1e-10 * nT2
+        assert abs(O.rel_error_identity(nT2, G) - e) < 1e-10
+        tails = []
+        for n in range(4):
+            w = np.sort(np.linalg.eigvalsh(O.gram(T, n)))[::-1]
+            tails.append(float(np.sum(w[K[n]:])))
+        assert e * e * nT2 <= sum(tails) * (1 + 1e-12)
+        # the factors are orthonormal and the core is T projected on them
+        for n in range(4):
+            assert np.abs(F[n].T @ F[n] - np.eye(K[n])).max() < 1e-13
+        assert np.allclose(G, O.new_core(T, F), atol=1e-12 * np.sqrt(nT2))
