@@ -128,6 +128,32 @@ int tk_plan_workspace(const tk_plan* plan, int rank, uint64_t* elements);
 int tk_plan_select(tk_plan* plan, int rank);
 void tk_plan_free(tk_plan* plan);
 
+/* ---- processor grids (host only; Sec. 4) ----------------------------------- */
+
+/* Number of N-dimensional grids of P processors, psi(P, N) =
+ * prod_i C(e_i + N - 1, N - 1) for P = prod_i p_i^e_i (Sec. 4.2).  TK_EINVAL
+ * for P < 1, N < 1 or a count above 2^64. */
+int tk_grid_count(int64_t P, int N, uint64_t* count);
+
+#define TK_GRID_STATIC 0   /* one grid for every tensor of the tree (Sec. 4.2)   */
+#define TK_GRID_DYNAMIC 1  /* a grid per node, regridding allowed (Sec. 4.3-4.4) */
+
+/* Processor grids for tree `rank` of `plan` on P processors.  A grid
+ * <q_1..q_N> (prod q_n = P) is valid when q_n <= K_n for every mode; a TTM
+ * along mode n at node u costs (q_n - 1) |Out(u)| words (Sec. 4.1).
+ *   TK_GRID_STATIC:  the valid grid with the least total TTM volume;
+ *   TK_GRID_DYNAMIC: the optimal scheme of Sec. 4.4: each node keeps its
+ *     parent's grid or redistributes its input (|In(u)| words) to a grid of
+ *     its own; T is laid out under a grid of free choice.
+ * Ties go to the lexicographically first grid, and to keeping the parent's.
+ * Out (host, nullable): root_grid[N] (the grid of T), node_grids[cap x N]
+ * (the grid of every node of tk_plan_nodes, in that order; leaves repeat
+ * their parent's), *volume (words).  Errors: TK_EINVAL (null plan, bad rank,
+ * P < 1, cap below the node count, unknown kind, volume above 2^64),
+ * TK_EUNSUPPORTED (no valid grid, or more than 2^22 grids to search). */
+int tk_plan_grids(const tk_plan* plan, int rank, int64_t P, int kind, int* root_grid,
+                  int* node_grids, int cap, uint64_t* volume);
+
 /* ---- HOOI context ---------------------------------------------------------- */
 
 /* Create a context for HOOI on the tensor T.
@@ -152,6 +178,21 @@ void tk_plan_free(tk_plan* plan);
 int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, const void* T_dev,
               const tk_plan* plan, int compute, const double* F0_host, void* stream,
               tk_ctx** out);
+
+/* As hooi_init, starting from the STHOSVD decomposition (Sec. 1 and
+ * Sec. 2.2: the initial decomposition is sequentially truncated HOSVD) instead
+ * of HOSVD: the modes are processed in `order` (host array of N distinct
+ * modes; NULL = ascending), mode n taking the leading K_n eigenvectors of the
+ * Gram of the current tensor's mode-n unfolding (FP64, as hooi_init's) and
+ * truncating the tensor along n (TTM at FP64 for FP64 storage, else FP32)
+ * before the next mode.  Allocates temporary device memory for the truncated
+ * tensors (at most |T| K_n / L_n elements, twice), synchronises the stream,
+ * then creates the context exactly as hooi_init with these factors.
+ * Errors: those of hooi_init, TK_EINVAL for an order that is not a
+ * permutation, TK_ENUMERIC from the eigensolver. */
+int hooi_init_sthosvd(int N, const int64_t* L, const int64_t* K, int tdtype, const void* T_dev,
+                      const tk_plan* plan, int compute, const int* order, void* stream,
+                      tk_ctx** out);
 
 /* Run `iters` >= 1 HOOI invocations (Fig. 2, Jacobi form: every chain uses the
  * factors from the start of the invocation).  rel_err: NULL or a host array of
@@ -312,6 +353,18 @@ int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute, doubl
 int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int64_t B,
            const void* F, int64_t K, void* out, void* stream);
 
+/* Both children of a TTM-tree root in one pass over the input (Sec. 3.1: a
+ * node's output -- here T -- is reused by all its children).  With `in`
+ * viewed row-major as [A, Lp, M, Lq, B] (device, FP32):
+ *   outp[a, kp, m, lq, b] = sum_lp Fp[lp, kp] in[a, lp, m, lq, b]   ([A, Kp, M, Lq, B])
+ *   outq[a, lp, m, kq, b] = sum_lq Fq[lq, kq] in[a, lp, m, lq, b]   ([A, Lp, M, Kq, B])
+ * Fp: Lp x Kp, Fq: Lq x Kq row-major FP32, device.  compute: TK_C_FP32.
+ * Requirements (else TK_EUNSUPPORTED): B % 4 == 0, Lq <= 256, Kp, Kq <= 20,
+ * 16-byte aligned pointers, A * M * B / 4 >= 2048.  Asynchronous on `stream`. */
+int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
+                int64_t Lq, int64_t B, const void* Fp, int64_t Kp, const void* Fq, int64_t Kq,
+                void* outp, void* outq, void* stream);
+
 /* Gram (Sec. 5): with Y viewed as [A, L, B], S[i, j] = sum_{a,b} Y[a,i,b] Y[a,j,b],
  * written as a full symmetric L x L FP64 matrix to device memory S.
  * in_dtype: TK_F64 (FP64 arithmetic) or TK_F32 (FP32 products, FP64 sums of
@@ -321,11 +374,27 @@ int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double
 
 /* Leading K eigenpairs of `count` symmetric L x L FP64 matrices (device,
  * contiguous), eigenvalues descending, each eigenvector's largest-magnitude
- * entry (lowest index on ties) made positive.  V0: NULL (cold start) or
- * device L x K start blocks (warm start, e.g. the previous factors).
- * F: device count x L x K row-major; evals: device count x K.  L <= 1024. */
+ * entry (lowest index on ties) made positive (Sec. 2.2: the new factor is the
+ * leading K_n left singular vectors of Y_(n), from its Gram matrix, Sec. 5).
+ * Subspace iteration (K <= 48, L <= 1024) from V0: NULL (cold start) or
+ * device L x K start blocks (warm start, e.g. the previous factors); a matrix
+ * whose solve does not converge (no eigen-gap at K), and every matrix when
+ * K > 48 or L > 1024, goes through the gap-free solver of tk_eig_full.
+ * F: device count x L x K row-major; evals: device count x K.  L <= 2048.
+ * Allocates its work areas per call and synchronises the stream.
+ * Errors: TK_EINVAL (sizes, null pointers), TK_EUNSUPPORTED (L > 2048),
+ * TK_ENUMERIC (non-finite values or no QL convergence), TK_EDEVICE. */
 int tk_eig_leading(int count, int L, int K, const double* S, const double* V0, double* F,
                    double* evals, void* stream);
+
+/* The gap-free solver alone (the route the paper's expert eigen-driver takes,
+ * Sec. 5): Householder tridiagonalisation of each S, implicit QL with
+ * Wilkinson shifts accumulating the eigenvectors of the tridiagonal matrix,
+ * the K largest eigenpairs back-transformed, sign rule as tk_eig_leading.
+ * Needs no gap at K and no start.  Same layouts, limits and errors as
+ * tk_eig_leading (1 <= K <= L <= 2048). */
+int tk_eig_full(int count, int L, int K, const double* S, double* F, double* evals,
+                void* stream);
 
 const char* tk_last_error(void);
 

@@ -65,6 +65,9 @@ _SIGS = {
     "tk_plan_free": ([_vp], None),
     "hooi_init": ([ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp, _vp, ctypes.c_int, _dp, _vp,
                    ctypes.POINTER(_vp)], ctypes.c_int),
+    "hooi_init_sthosvd": ([ctypes.c_int, _i64p, _i64p, ctypes.c_int, _vp, _vp, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_int), _vp, ctypes.POINTER(_vp)],
+                          ctypes.c_int),
     "hooi_iterate": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
     "tucker_error": ([_vp, _dp, _dp, _dp], ctypes.c_int),
     "tucker_error_explicit": ([_vp, _dp], ctypes.c_int),
@@ -80,8 +83,15 @@ _SIGS = {
     "tk_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _vp],
                ctypes.c_int),
     "tk_gram": ([ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp], ctypes.c_int),
+    "tk_grid_count": ([_i64, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "tk_plan_grids": ([_vp, ctypes.c_int, _i64, ctypes.c_int, _ip, _ip, ctypes.c_int,
+                       ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "tk_ttm_pair": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64,
+                     _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "tk_eig_leading": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
                        ctypes.c_int),
+    "tk_eig_full": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp],
+                    ctypes.c_int),
     "tk_ttm_features": ([_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _fp],
                         ctypes.c_int),
     "tk_time_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp,
@@ -211,6 +221,20 @@ class Plan:
         _check(lib().tk_plan_get_tiles(self._h, rank, arr, n.value, ctypes.byref(n)))
         return list(arr)
 
+    def grids(self, P, kind="dynamic", rank=0):
+        """Processor grids for P processors (Sec. 4): (volume, root grid,
+        per-node grids in nodes() order); kind "static" or "dynamic"."""
+        N = len(self.L)
+        n = len(self.nodes(rank))
+        root = (ctypes.c_int * N)()
+        per = (ctypes.c_int * (n * N))()
+        vol = ctypes.c_uint64()
+        _check(lib().tk_plan_grids(self._h, int(rank), int(P),
+                                   {"static": 0, "dynamic": 1}[kind], root, per, n,
+                                   ctypes.byref(vol)))
+        return (int(vol.value), tuple(root),
+                [tuple(per[u * N:(u + 1) * N]) for u in range(n)])
+
     def learned(self, model, tdtype="f32", compute="fp32", margin=0.02):
         """Select a held tree and per-node kernels by the cost model; returns
         (chosen rank, predicted ms per rank)."""
@@ -221,6 +245,13 @@ class Plan:
                                      float(margin), ctypes.byref(chosen),
                                      pred.ctypes.data_as(_dp)))
         return chosen.value, pred
+
+
+def grid_count(P, N):
+    """psi(P, N): the number of N-dimensional grids of P processors (Sec. 4.2)."""
+    c = ctypes.c_uint64()
+    _check(lib().tk_grid_count(int(P), int(N), ctypes.byref(c)))
+    return int(c.value)
 
 
 def ttm_tree_plan(L, K, kind="dp", topk=1) -> Plan:
@@ -263,7 +294,8 @@ def _dev_ptr(t):
 class Context:
     """HOOI context on a device tensor T (borrowed: keep T alive)."""
 
-    def __init__(self, T, K, plan=None, compute="fp32", F0=None, stream=None):
+    def __init__(self, T, K, plan=None, compute="fp32", F0=None, stream=None, init="hosvd",
+                 order=None):
         import numpy as np
         self.T = T
         self.L = tuple(int(x) for x in T.shape)
@@ -277,10 +309,23 @@ class Context:
             self._f0 = flat
             f0p = flat.ctypes.data_as(_dp)
         h = _vp()
-        _check(lib().hooi_init(self.N, _arr64(self.L), _arr64(self.K), _dtype_code(T),
-                               _dev_ptr(T), plan.handle if plan is not None else None,
-                               COMPUTE[compute] if isinstance(compute, str) else int(compute),
-                               f0p, _stream_ptr(stream), ctypes.byref(h)))
+        comp = COMPUTE[compute] if isinstance(compute, str) else int(compute)
+        if init == "sthosvd":
+            if F0 is not None:
+                raise ValueError("F0 and init='sthosvd' exclude each other")
+            ordp = None
+            if order is not None:
+                ordp = (ctypes.c_int * self.N)(*[int(n) for n in order])
+            _check(lib().hooi_init_sthosvd(self.N, _arr64(self.L), _arr64(self.K),
+                                           _dtype_code(T), _dev_ptr(T),
+                                           plan.handle if plan is not None else None, comp,
+                                           ordp, _stream_ptr(stream), ctypes.byref(h)))
+        elif init == "hosvd":
+            _check(lib().hooi_init(self.N, _arr64(self.L), _arr64(self.K), _dtype_code(T),
+                                   _dev_ptr(T), plan.handle if plan is not None else None,
+                                   comp, f0p, _stream_ptr(stream), ctypes.byref(h)))
+        else:
+            raise ValueError(f"unknown init {init!r}")
         self._h = h
 
     def __del__(self):
@@ -355,9 +400,12 @@ class Context:
         return list(arr)
 
 
-def hooi_init(T, K, plan=None, compute="fp32", F0=None, stream=None) -> Context:
-    """Create a HOOI context: HOSVD start unless F0 (list of L_n x K_n) is given."""
-    return Context(T, K, plan=plan, compute=compute, F0=F0, stream=stream)
+def hooi_init(T, K, plan=None, compute="fp32", F0=None, stream=None, init="hosvd",
+              order=None) -> Context:
+    """Create a HOOI context: HOSVD start (init="hosvd") unless F0 (list of
+    L_n x K_n) is given, or STHOSVD (init="sthosvd", modes in `order`)."""
+    return Context(T, K, plan=plan, compute=compute, F0=F0, stream=stream, init=init,
+                   order=order)
 
 
 def hooi_iterate(ctx: Context, iters=1):
@@ -375,6 +423,14 @@ def ttm(inp, A, L, B, F, K, out, compute="fp32", stream=None):
     """Out[a,k,b] = sum_l F[l,k] In[a,l,b] on device tensors."""
     _check(lib().tk_ttm(_dtype_code(inp), COMPUTE[compute], _dev_ptr(inp), int(A), int(L),
                         int(B), _dev_ptr(F), int(K), _dev_ptr(out), _stream_ptr(stream)))
+
+
+def ttm_pair(inp, A, Lp, M, Lq, B, Fp, Kp, Fq, Kq, outp, outq, compute="fp32", stream=None):
+    """Both root TTMs of `inp` viewed as [A, Lp, M, Lq, B] in one pass."""
+    _check(lib().tk_ttm_pair(_dtype_code(inp), COMPUTE[compute], _dev_ptr(inp), int(A),
+                             int(Lp), int(M), int(Lq), int(B), _dev_ptr(Fp), int(Kp),
+                             _dev_ptr(Fq), int(Kq), _dev_ptr(outp), _dev_ptr(outq),
+                             _stream_ptr(stream)))
 
 
 def gram(Y, A, L, B, S, stream=None):
@@ -396,6 +452,21 @@ def eig_leading(S, K, V0=None, F=None, evals=None, stream=None):
     _check(lib().tk_eig_leading(count, L, K, _dev_ptr(S),
                                 _dev_ptr(V0) if V0 is not None else None, _dev_ptr(F),
                                 _dev_ptr(evals), _stream_ptr(stream)))
+    return F, evals
+
+
+def eig_full(S, K, F=None, evals=None, stream=None):
+    """Leading K eigenpairs by the gap-free solver (tridiagonalisation + QL)."""
+    torch = _torch()
+    if S.dim() == 2:
+        S = S.unsqueeze(0)
+    count, L, _ = S.shape
+    if F is None:
+        F = torch.empty((count, L, K), dtype=torch.float64, device=S.device)
+    if evals is None:
+        evals = torch.empty((count, K), dtype=torch.float64, device=S.device)
+    _check(lib().tk_eig_full(count, L, K, _dev_ptr(S), _dev_ptr(F), _dev_ptr(evals),
+                             _stream_ptr(stream)))
     return F, evals
 
 

@@ -94,6 +94,11 @@ struct tk_batch {
     int job0, count, Lmax, pmax;
   };
   std::vector<EigClass> warm_classes, cold_classes;
+  // gap-free solver (eigfull.hip) for the subspace jobs (L > 64) whose solve
+  // did not converge: one conditional launch after the eigensolve classes
+  EigFullJob* fjobs = nullptr;
+  double* fwork = nullptr;
+  int n_fjobs = 0, fLmax = 0, fKmax = 0;
   float* core = nullptr;
   int64_t* core_off = nullptr;
   double* normG2 = nullptr;
@@ -126,7 +131,8 @@ struct tk_batch {
     void* ptrs[] = {ws,        Fc,        F64a,       F64b,     S,          ev,
                     eigwork,   basis,     status,     jobs_warm, jobs_cold, core,
                     core_off,  normG2,    normT2_dev, sumsq_part, ttm_nodes, ttm_items,
-                    counters,  gram,      gram_items, gram_off,  gpart};
+                    counters,  gram,      gram_items, gram_off,  gpart,     fjobs,
+                    fwork};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     if (st) (void)hipStreamDestroy(st);
@@ -194,6 +200,8 @@ int enqueue_iteration(tk_batch* b) {
     TK_HIP(hipEventRecord(b->ev_join[k], b->aux[k]));
     TK_HIP(hipStreamWaitEvent(b->st, b->ev_join[k], 0));
   }
+  TK_HIP(launch_eig_full(b->n_fjobs, b->fjobs, b->fLmax, b->fKmax, b->S, b->F64b, b->ev,
+                         b->fwork, b->status, b->st));
   TK_HIP(launch_copy_f64(b->F64b, b->F64a, b->nF, b->st));
   TK_HIP(launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, b->st));
   return TK_OK;
@@ -583,6 +591,30 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     classes(jc, jw, &b->cold_classes);
   }
   b->jobs_h = jc;
+  // subspace jobs (p < L) may fall back to the gap-free solver; job q of the
+  // (sorted) tables owns status word q
+  std::vector<EigFullJob> fj;
+  int64_t fwork = 0;
+  for (int q = 0; q < b->n_jobs; ++q) {
+    const EigJob& j = jc[q];
+    if (j.p == j.L) continue;
+    EigFullJob f;
+    f.L = j.L;
+    f.K = j.K;
+    f.status_idx = q;
+    f.only_if_failed = 1;
+    f.S_off = j.S_off;
+    f.F_off = j.F_off;
+    f.ev_off = j.ev_off;
+    f.work_off = fwork;
+    fwork += (int64_t)eig_full_work_elems(j.L);
+    b->fLmax = std::max(b->fLmax, j.L);
+    b->fKmax = std::max(b->fKmax, j.K);
+    fj.push_back(f);
+  }
+  b->n_fjobs = (int)fj.size();
+  if (b->n_fjobs > 0 && ((rc = dalloc_t(&b->fwork, (size_t)fwork)) || (rc = upload(&b->fjobs, fj, st))))
+    return bail(rc);
   if (nbasis > 0) {
     std::vector<double> ident;
     eig_identity_bases(jc, &ident);
@@ -623,6 +655,9 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     e = launch_eig(c.count, b->jobs_cold, c.job0, c.Lmax, c.pmax, b->S, b->F64a, b->F64a, b->ev,
                    b->eigwork, b->status, nullptr, 100, 1e-11, st, b->basis);
   }
+  if (e == hipSuccess)
+    e = launch_eig_full(b->n_fjobs, b->fjobs, b->fLmax, b->fKmax, b->S, b->F64a, b->ev,
+                        b->fwork, b->status, st);
   if (e == hipSuccess) e = launch_convert(TK_F64, TK_F32, b->F64a, b->Fc, b->nF, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->normT2.data(), b->normT2_dev, sizeof(double) * count,

@@ -1,0 +1,405 @@
+// Leading eigenpairs of a symmetric FP64 matrix without any assumption on the
+// eigenvalue gaps (the EVD after the Gram product, Sec. 5; the paper takes
+// the leading K_n eigenvectors with an expert driver that tridiagonalises,
+// bisects and inverse-iterates).  Used where subspace iteration is not enough:
+// K above its block limit, or a solve that did not converge (no gap at K).
+//
+// Method (one workgroup per matrix for the first kernel):
+//   1. Householder tridiagonalisation  Q^T S Q = tridiag(d, e),
+//      Q = H_0 H_1 ... H_{L-3},  H_j = I - tau_j v_j v_j^T acting on rows
+//      j+1 .. L-1 (v_j stored in row j of the work copy of S, v_j[j+1] = 1).
+//   2. Implicit QL iteration with Wilkinson shifts on (d, e), accumulating
+//      the plane rotations into Z (eigenvectors of the tridiagonal matrix);
+//      one thread chases the bulge and records the rotations, then every
+//      thread applies them to its rows of Z.
+//   3. Ranks of the eigenvalues (descending, lower index first on ties): the
+//      K largest and their columns of Z.
+// A second kernel (a grid of column blocks per matrix) applies Q to the K
+// selected columns (reflectors in reverse order, the block in LDS) and the
+// sign rule (largest-magnitude entry of each vector positive, lowest row on
+// ties).
+//
+// Work area per matrix (eig_full_work_elems): A (L x L), Zt (L x L, Zt[i][r] =
+// Z[r][i], so a rotation of columns i, i+1 of Z reads two rows), d, e, tau,
+// the selection (as doubles), 4 L, and a done flag that the first kernel sets
+// (1: solved in this launch) and the second reads.
+//
+// Status word of a job: 0 solved, 1 not converged, 2 non-finite values.  A
+// job marked only_if_failed runs only when its status word is 1 (the
+// subspace solve before it did not converge) and otherwise leaves F alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "device.h"
+#include "internal.h"
+#include "kernels.h"
+
+namespace tk {
+
+constexpr int kFullThreads = 256;
+constexpr int kFullMaxL = 2048;
+constexpr int kQlMaxSweeps = 60;  // per eigenvalue
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kFullThreads / 64; ++w) s += red[w];
+  return s;
+}
+
+struct FullShared {
+  double red[kFullThreads / 64];
+  double scal[4];
+  int flag, lo;
+};
+
+__global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
+    const EigFullJob* __restrict__ jobs, const double* __restrict__ S_base,
+    double* __restrict__ ev_base, double* __restrict__ work_base, int* __restrict__ status) {
+  extern __shared__ double lds[];  // v, w (L each), rotation cosines, sines (L each)
+  __shared__ FullShared sh;
+  const EigFullJob job = jobs[blockIdx.x];
+  const int L = job.L, K = job.K, tid = threadIdx.x;
+  double* A = work_base + job.work_off;
+  double* Zt = A + (int64_t)L * L;
+  double* d = Zt + (int64_t)L * L;
+  double* e = d + L;
+  double* tau = e + L;
+  double* sel = tau + L;
+  double* done = sel + L;
+  if (job.only_if_failed && status[job.status_idx] != 1) {  // nothing to redo
+    if (tid == 0) *done = 0.0;
+    return;
+  }
+  const double* S = S_base + job.S_off;
+  double* v = lds;
+  double* w = lds + L;
+  double* cs = lds + 2 * L;
+  double* sn = lds + 3 * L;
+
+  for (int64_t i = tid; i < (int64_t)L * L; i += kFullThreads) A[i] = S[i];
+  __syncthreads();
+
+  // ---- 1. Householder reduction to tridiagonal form
+  for (int j = 0; j + 2 < L; ++j) {
+    const int m = L - j - 1;  // length of the column below the diagonal
+    double* row = A + (int64_t)j * L + j + 1;  // = that column, by symmetry
+    double part = 0.0;
+    for (int k = 1 + tid; k < m; k += kFullThreads) part = fma(row[k], row[k], part);
+    const double sigma = block_sum(part, sh.red);
+    const double alpha = row[0];
+    if (tid == 0) {
+      double t = 0.0, v0 = 1.0, beta = alpha;
+      if (sigma > 0.0) {
+        const double mu = sqrt(alpha * alpha + sigma);
+        v0 = alpha <= 0.0 ? alpha - mu : -sigma / (alpha + mu);
+        t = 2.0 * v0 * v0 / (sigma + v0 * v0);
+        beta = mu;
+      }
+      d[j] = A[(int64_t)j * L + j];
+      e[j] = beta;
+      tau[j] = t;
+      sh.scal[0] = t;
+      sh.scal[1] = 1.0 / v0;
+    }
+    __syncthreads();
+    const double t = sh.scal[0];
+    if (t == 0.0) {
+      if (tid == 0) row[0] = 1.0;  // H_j = I; the stored vector is never used
+      __syncthreads();
+      continue;
+    }
+    const double inv = sh.scal[1];
+    for (int k = tid; k < m; k += kFullThreads) {
+      const double vk = k == 0 ? 1.0 : row[k] * inv;
+      v[k] = vk;
+    }
+    __syncthreads();
+    for (int k = tid; k < m; k += kFullThreads) row[k] = v[k];  // kept for the back-transform
+    // p = tau * A' v over the trailing block A' (rows/columns j+1 ..), column
+    // by column through the symmetric rows, which keeps the loads coalesced
+    double* Ap = A + (int64_t)(j + 1) * L + (j + 1);
+    for (int i = tid; i < m; i += kFullThreads) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int k = 0;
+      for (; k + 4 <= m; k += 4) {
+        s0 = fma(Ap[(int64_t)k * L + i], v[k], s0);
+        s1 = fma(Ap[(int64_t)(k + 1) * L + i], v[k + 1], s1);
+        s2 = fma(Ap[(int64_t)(k + 2) * L + i], v[k + 2], s2);
+        s3 = fma(Ap[(int64_t)(k + 3) * L + i], v[k + 3], s3);
+      }
+      for (; k < m; ++k) s0 = fma(Ap[(int64_t)k * L + i], v[k], s0);
+      w[i] = t * ((s0 + s1) + (s2 + s3));
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int k = tid; k < m; k += kFullThreads) pv = fma(w[k], v[k], pv);
+    const double half = 0.5 * t * block_sum(pv, sh.red);
+    for (int k = tid; k < m; k += kFullThreads) w[k] = w[k] - half * v[k];
+    __syncthreads();
+    // A' -= v w^T + w v^T
+    for (int k = 0; k < m; ++k) {
+      const double vk = v[k], wk = w[k];
+      double* Ar = Ap + (int64_t)k * L;
+      for (int i = tid; i < m; i += kFullThreads) Ar[i] = Ar[i] - vk * w[i] - wk * v[i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (L >= 2) {
+      d[L - 2] = A[(int64_t)(L - 2) * L + (L - 2)];
+      e[L - 2] = A[(int64_t)(L - 2) * L + (L - 1)];
+    }
+    d[L - 1] = A[(int64_t)(L - 1) * L + (L - 1)];
+    e[L - 1] = 0.0;
+    sh.flag = 0;
+    // deflation threshold relative to the matrix norm (max_i |d_i| + |e_i|):
+    // a test relative to the two neighbouring diagonal entries stalls when
+    // small eigenvalues sit beside large ones (rounding leaves off-diagonal
+    // entries of order eps ||S||)
+    double tst = 0.0;
+    for (int i = 0; i < L; ++i) tst = fmax(tst, fabs(d[i]) + fabs(e[i]));
+    sh.scal[3] = tst;
+  }
+  for (int64_t i = tid; i < (int64_t)L * L; i += kFullThreads)
+    Zt[i] = (i / L == i % L) ? 1.0 : 0.0;
+  __syncthreads();
+
+  // ---- 2. implicit QL with Wilkinson shifts; Z accumulates the rotations
+  const double thresh = 2.220446049250313e-16 * sh.scal[3];
+  for (int l = 0; l < L; ++l) {
+    for (int sweep = 0;; ++sweep) {
+      if (tid == 0) {
+        int m = l;
+        while (m < L - 1 && fabs(e[m]) > thresh) ++m;
+        int lo = m;  // lowest rotated index; m == l: converged
+        if (m != l) {
+          if (sweep >= kQlMaxSweeps) {
+            sh.flag = 1;
+          } else {
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool split = false;
+            for (int i = m - 1; i >= l; --i) {
+              const double f = s * e[i];
+              const double b = c * e[i];
+              r = hypot(f, g);
+              e[i + 1] = r;
+              if (r == 0.0) {  // underflow: the matrix splits here, restart
+                d[i + 1] -= p;
+                e[m] = 0.0;
+                split = true;
+                break;
+              }
+              s = f / r;
+              c = g / r;
+              g = d[i + 1] - p;
+              r = (d[i] - g) * s + 2.0 * c * b;
+              p = s * r;
+              d[i + 1] = g + p;
+              g = c * r - b;
+              cs[i] = c;
+              sn[i] = s;
+              lo = i;
+            }
+            if (!split) {
+              d[l] -= p;
+              e[l] = g;
+              e[m] = 0.0;
+            }
+          }
+        }
+        sh.lo = lo;
+        sh.scal[2] = (double)m;
+      }
+      __syncthreads();
+      const int m = (int)sh.scal[2];
+      const int lo = sh.lo;
+      if (sh.flag) break;
+      if (m == l) break;
+      // columns lo .. m of Z: rotation i mixes columns i and i+1, applied for
+      // i = m-1 down to lo; each thread carries column i+1 of its rows
+      if (lo < m) {
+        for (int r = tid; r < L; r += kFullThreads) {
+          double znext = Zt[(int64_t)m * L + r];
+          for (int i = m - 1; i >= lo; --i) {
+            const double zi = Zt[(int64_t)i * L + r];
+            const double c = cs[i], s = sn[i];
+            Zt[(int64_t)(i + 1) * L + r] = s * zi + c * znext;
+            znext = c * zi - s * znext;
+          }
+          Zt[(int64_t)lo * L + r] = znext;
+        }
+      }
+      __syncthreads();
+    }
+    if (sh.flag) break;
+  }
+  __syncthreads();
+
+  // ---- 3. the K largest eigenvalues, descending (lower index first on ties)
+  int bad = 0;
+  for (int j = tid; j < L; j += kFullThreads) {
+    const double dj = d[j];
+    bad |= !isfinite(dj);
+    int rank = 0;
+    for (int i = 0; i < L; ++i) {
+      const double di = d[i];
+      rank += (di > dj) || (di == dj && i < j);
+    }
+    if (rank < K) sel[rank] = (double)j;
+  }
+  bad = __syncthreads_or(bad);
+  __syncthreads();
+  double* ev = ev_base + job.ev_off;
+  for (int c = tid; c < K; c += kFullThreads) ev[c] = d[(int)sel[c]];
+  if (tid == 0) {
+    status[job.status_idx] = bad ? 2 : (sh.flag ? 1 : 0);
+    *done = (bad || sh.flag) ? 0.0 : 1.0;
+  }
+}
+
+// Back-transformation of VB selected columns per block: Y = Q Z[:, sel], then
+// the sign rule, written to F (L x K row-major).
+__global__ __launch_bounds__(kFullThreads) void eig_full_backtransform(
+    const EigFullJob* __restrict__ jobs, double* __restrict__ F_base,
+    const double* __restrict__ work_base, int VB) {
+  extern __shared__ double lds[];
+  const EigFullJob job = jobs[blockIdx.x];
+  const int L = job.L, K = job.K, tid = threadIdx.x;
+  const int c0 = blockIdx.y * VB;
+  if (c0 >= K) return;
+  const int nc = min(VB, K - c0);
+  const double* A = work_base + job.work_off;
+  const double* Zt = A + (int64_t)L * L;
+  const double* tau = Zt + (int64_t)L * L + 2 * L;
+  const double* sel = tau + L;
+  if (sel[L] != 1.0) return;  // not solved in this launch
+  double* Y = lds;             // L x VB
+  double* v = lds + L * VB;    // L
+  double* red = v + L;         // kFullThreads
+  int* redi = reinterpret_cast<int*>(red + kFullThreads);  // kFullThreads
+  for (int e = tid; e < L * VB; e += kFullThreads) {
+    const int pos = e / VB, c = e % VB;
+    Y[e] = c < nc ? Zt[(int64_t)(int)sel[c0 + c] * L + pos] : 0.0;
+  }
+  __syncthreads();
+  const int nparts = kFullThreads / VB;
+  const int cc = tid % VB, part = tid / VB;
+  for (int j = L - 3; j >= 0; --j) {
+    const double t = tau[j];
+    if (t == 0.0) continue;
+    const int b = j + 1, m = L - b;
+    const double* row = A + (int64_t)j * L + b;
+    for (int k = tid; k < m; k += kFullThreads) v[b + k] = row[k];
+    __syncthreads();
+    double s = 0.0;
+    for (int pos = b + part; pos < L; pos += nparts) s = fma(v[pos], Y[pos * VB + cc], s);
+    red[tid] = s;
+    __syncthreads();
+    // thread c < VB sums the parts of column c (entries c, VB + c, ...) and
+    // leaves tau * (v^T y_c) in red[c], an entry only it reads
+    if (tid < VB) {
+      double acc = 0.0;
+      for (int q = 0; q < nparts; ++q) acc += red[q * VB + tid];
+      red[tid] = t * acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * VB; e += kFullThreads) {
+      const int pos = b + e / VB, c = e % VB;
+      Y[pos * VB + c] -= v[pos] * red[c];
+    }
+    __syncthreads();
+  }
+  // sign rule per column
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int pos = part; pos < L; pos += nparts) {
+    const double a = fabs(Y[pos * VB + cc]);
+    if (a > best || (a == best && pos < bi)) {
+      best = a;
+      bi = pos;
+    }
+  }
+  red[tid] = best;
+  redi[tid] = bi;
+  __syncthreads();
+  if (tid < VB) {
+    double b0 = red[tid];
+    int i0 = redi[tid];
+    for (int q = 1; q < nparts; ++q) {
+      const double ob = red[q * VB + tid];
+      const int oi = redi[q * VB + tid];
+      if (ob > b0 || (ob == b0 && oi < i0)) {
+        b0 = ob;
+        i0 = oi;
+      }
+    }
+    red[tid] = Y[i0 * VB + tid] < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  double* F = F_base + job.F_off;
+  for (int e = tid; e < L * VB; e += kFullThreads) {
+    const int pos = e / VB, c = e % VB;
+    if (c < nc) F[(int64_t)pos * K + c0 + c] = red[c] * Y[e];
+  }
+}
+
+namespace {
+
+int full_vb(int Lmax) {
+  // Y (L x VB) + v (L) + the reductions (1.5 kFullThreads) in at most 144 KB
+  const int budget = 144 * 1024 / 8 - 2 * kFullThreads - Lmax;
+  int vb = 32;
+  while (vb > 1 && vb * Lmax > budget) vb /= 2;
+  return vb;
+}
+
+bool g_full_attr = false;
+
+hipError_t full_attrs() {
+  if (g_full_attr) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void*)eig_full_tridiag_ql,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     4 * kFullMaxL * (int)sizeof(double));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)eig_full_backtransform,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 144 * 1024);
+  if (e == hipSuccess) g_full_attr = true;
+  return e;
+}
+
+}  // namespace
+
+int eig_full_max_L() { return kFullMaxL; }
+
+size_t eig_full_work_elems(int L) { return (size_t)2 * L * L + 4 * (size_t)L + 1; }
+
+hipError_t launch_eig_full(int count, const EigFullJob* jobs_dev, int Lmax, int Kmax,
+                           const double* S_base, double* F_base, double* ev_base,
+                           double* work_base, int* status, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  if (Lmax < 1 || Lmax > kFullMaxL || Kmax < 1) return hipErrorInvalidValue;
+  hipError_t e = full_attrs();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(eig_full_tridiag_ql, dim3(count), dim3(kFullThreads),
+                     4 * (size_t)Lmax * sizeof(double), st, jobs_dev, S_base, ev_base, work_base,
+                     status);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int vb = full_vb(Lmax);
+  const size_t lds = sizeof(double) * ((size_t)Lmax * vb + Lmax + 2 * kFullThreads);
+  hipLaunchKernelGGL(eig_full_backtransform, dim3(count, (Kmax + vb - 1) / vb),
+                     dim3(kFullThreads), lds, st, jobs_dev, F_base, work_base, vb);
+  return hipGetLastError();
+}
+
+}  // namespace tk

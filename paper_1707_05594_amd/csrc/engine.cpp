@@ -82,6 +82,11 @@ struct tk_ctx {
   Tree tree;
   std::vector<int64_t> node_off;  // element offset of each internal node's output in ws
   std::vector<int> chain_order;   // mode order of the direct core chain
+  // Both root children formed by one pass over T (ttm_pair): their indices
+  // (pair_u[0] multiplies the lower mode) or -1.  The second child's subtree
+  // then sits after the first's in the workspace, since both outputs are live
+  // at once.
+  int pair_u[2] = {-1, -1};
   int fold_leaf = 0;              // leaf whose Y folds the core
   int64_t ws_elems = 0, chain_a = 0;
   size_t fofs[TK_MAX_MODES + 1] = {};
@@ -101,6 +106,14 @@ struct tk_ctx {
   EigJob* jobs = nullptr;   // device job table, warm start from F64a
   EigJob* jobs_cold = nullptr;
   std::vector<EigJob> jobs_h;
+  // Gap-free solver (eigfull.hip): one job per mode.  A mode whose K exceeds
+  // the subspace block limit (full_only) always takes it; every other mode
+  // takes it only after a subspace solve that did not converge, so no
+  // unconverged factor is ever adopted.
+  EigFullJob* fjobs = nullptr;
+  double* fwork = nullptr;
+  bool full_only[TK_MAX_MODES] = {};
+  int fLmax = 0, fKmax = 0;
   double* gpart = nullptr;  // Gram chunk partials
   size_t gpart_elems = 0;
   double* rpart = nullptr;  // reduction partials
@@ -142,7 +155,7 @@ struct tk_ctx {
     if (own_main) (void)hipStreamSynchronize(st);
     void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc,
                     wdtype == TK_F64 ? nullptr : Fcb, S, ev, eigwork, status, jobs,
-                    jobs_cold, gpart, rpart, scal, core};
+                    jobs_cold, gpart, rpart, scal, core, fjobs, fwork};
     for (void* p : ptrs)
       if (p) (void)hipFree(p);
     for (void* p : leaves)
@@ -233,10 +246,28 @@ hipError_t create_streams(tk_ctx* c) {
   return hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
 }
 
+// Every mode's leading eigenpairs on the main stream: subspace iteration
+// (one launch over all modes when every mode takes it), then the gap-free
+// solver for the full-only modes and for any solve that did not converge.
 int run_eig(tk_ctx* c, bool warm, double* F_out, int maxit) {
-  TK_HIP(launch_eig(c->s.N, warm ? c->jobs : c->jobs_cold, 0, c->Lmax, c->pmax, c->S, c->F64a,
-                    F_out, c->ev, c->eigwork, c->status, c->status + c->s.N, maxit, c->eig_tol,
-                    c->st));
+  const int N = c->s.N;
+  bool any_full = false;
+  for (int n = 0; n < N; ++n) any_full = any_full || c->full_only[n];
+  if (!any_full) {
+    TK_HIP(launch_eig(N, warm ? c->jobs : c->jobs_cold, 0, c->Lmax, c->pmax, c->S, c->F64a,
+                      F_out, c->ev, c->eigwork, c->status, c->status + N, maxit, c->eig_tol,
+                      c->st));
+  } else {
+    const std::vector<EigJob>& tab = c->jobs_h;
+    for (int n = 0; n < N; ++n) {
+      if (c->full_only[n]) continue;
+      TK_HIP(launch_eig(1, warm ? c->jobs : c->jobs_cold, n, tab[n].L, c->pmax, c->S, c->F64a,
+                        F_out, c->ev, c->eigwork, c->status, c->status + N, maxit, c->eig_tol,
+                        c->st));
+    }
+  }
+  TK_HIP(launch_eig_full(N, c->fjobs, c->fLmax, c->fKmax, c->S, F_out, c->ev, c->fwork,
+                         c->status, c->st));
   return TK_OK;
 }
 
@@ -304,6 +335,7 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
   const Shape& s = c->s;
   const auto& nodes = c->tree.nodes;
   const std::vector<int> order = exec_order(nodes, update && (c->passes % 2 == 1));
+  bool pair_done = false;
   for (int u : order) {
     const tk_node& nd = nodes[u];
     // the node reads factor nd.mode (a leaf also rewrites Gram buffer nd.mode,
@@ -314,7 +346,24 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
     int64_t A, L, B;
     view(s, nd.pre_mask, nd.mode, &A, &L, &B);
     if (ev_t) TK_HIP(hipEventRecord(ev_t[2 * u], c->st));
-    if (!nd.is_leaf) {
+    if (c->pair_u[0] >= 0 && (u == c->pair_u[0] || u == c->pair_u[1])) {
+      // both root children in one pass over T (the first of them to run
+      // launches it; the other has nothing left to do)
+      if (!pair_done) {
+        const int up = c->pair_u[0], uq = c->pair_u[1];
+        const int p = nodes[up].mode, q = nodes[uq].mode;
+        if (int rc = wait_factor(c, p)) return rc;
+        if (int rc = wait_factor(c, q)) return rc;
+        int64_t Ap, Lp, Bp, Aq, Lq, Bq;
+        view(s, 0, p, &Ap, &Lp, &Bp);
+        view(s, 0, q, &Aq, &Lq, &Bq);
+        TK_HIP(launch_ttm_pair((const float*)c->T, Ap, Lp, Aq / (Ap * Lp), Lq, Bq,
+                               (const float*)c->fc(p), s.K[p], (const float*)c->fc(q), s.K[q],
+                               (float*)c->wsp(c->node_off[up]), (float*)c->wsp(c->node_off[uq]),
+                               c->st));
+        pair_done = true;
+      }
+    } else if (!nd.is_leaf) {
       TK_HIP(launch_ttm(in_dt, c->node_compute[u], in, A, L, B, c->fc(nd.mode), s.K[nd.mode],
                         c->wsp(c->node_off[u]), c->st, c->node_stream[u], c->node_tile[u],
                         c->node_out_dt[u]));
@@ -328,8 +377,11 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
         TK_HIP(hipEventRecord(c->ev_leaf[n], c->st));
         TK_HIP(hipStreamWaitEvent(c->side, c->ev_leaf[n], 0));
         const EigJob& j = c->jobs_h[n];
-        TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, c->F64b, c->ev, c->eigwork,
-                          c->status, c->status + s.N, c->maxit_warm, c->eig_tol, c->side));
+        if (!c->full_only[n])
+          TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, c->F64b, c->ev, c->eigwork,
+                            c->status, c->status + s.N, c->maxit_warm, c->eig_tol, c->side));
+        TK_HIP(launch_eig_full(1, c->fjobs + n, j.L, j.K, c->S, c->F64b, c->ev, c->fwork,
+                               c->status, c->side));
         if (c->wdtype != TK_F64)
           TK_HIP(launch_convert(TK_F64, c->wdtype, c->F64b + c->fofs[n],
                                 (char*)c->Fcb + c->fofs[n] * dtype_size(c->wdtype),
@@ -405,12 +457,9 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if ((tdtype == TK_F64) != (compute == TK_C_FP64))
     return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
-  const int maxL = compute == TK_C_FP64 ? 512 : ttm_max_L();
-  for (int j = 0; j < N; ++j) {
+  const int maxL = std::min(compute == TK_C_FP64 ? 512 : ttm_max_L(), eig_full_max_L());
+  for (int j = 0; j < N; ++j)
     if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
-    if (s.K[j] > eig_max_K())
-      return fail(TK_EUNSUPPORTED, "K[%d]=%lld exceeds %d", j, (long long)s.K[j], eig_max_K());
-  }
   if (plan && !plan->shape.same(s)) return fail(TK_EINVAL, "plan was built for another shape");
 
   tk_ctx* c = new (std::nothrow) tk_ctx;
@@ -449,6 +498,42 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
         nd.parent < 0 ? 0 : align64(c->node_off[nd.parent] + (int64_t)nodes[nd.parent].out_card);
     c->node_off[u] = base;
     if (!nd.is_leaf) ws = std::max<int64_t>(ws, base + (int64_t)nd.out_card);
+  }
+  // both root children in one pass over T (TK_ROOT_PAIR=1): FP32 storage
+  // and compute, the automatic kernel choice, and a shape the pair kernel
+  // takes; the second child's subtree moves past the first's in the
+  // workspace.  Off by default: measured slower than two streaming root TTMs.
+  if (const char* v = getenv("TK_ROOT_PAIR"); v && atoi(v) == 1) {
+    std::vector<int> roots;
+    for (size_t u = 0; u < nodes.size(); ++u)
+      if (nodes[u].parent < 0) roots.push_back((int)u);
+    if (roots.size() == 2 && !nodes[roots[0]].is_leaf && !nodes[roots[1]].is_leaf &&
+        tdtype == TK_F32 && compute == TK_C_FP32 && c->node_tile[roots[0]] == TK_TILE_AUTO &&
+        c->node_tile[roots[1]] == TK_TILE_AUTO) {
+      int up = roots[0], uq = roots[1];
+      if (nodes[up].mode > nodes[uq].mode) std::swap(up, uq);
+      const int p = nodes[up].mode, q = nodes[uq].mode;
+      int64_t Ap, Lp, Bp, Aq, Lq, Bq;
+      view(s, 0, p, &Ap, &Lp, &Bp);
+      view(s, 0, q, &Aq, &Lq, &Bq);
+      // alignment of the outputs is that of the workspace (256 bytes) and its
+      // 64-element offsets; checked with representative aligned pointers
+      const void* al = (const void*)(uintptr_t)256;
+      if (ttm_pair_applies(TK_F32, TK_C_FP32, T_dev, Ap, Lp, Aq / (Ap * Lp), Lq, Bq, s.K[p],
+                           s.K[q], al, al)) {
+        const int second = std::max(roots[0], roots[1]);
+        int64_t w1 = 0;
+        for (int u = 0; u < second; ++u)
+          if (!nodes[u].is_leaf) w1 = std::max<int64_t>(w1, c->node_off[u] + (int64_t)nodes[u].out_card);
+        const int64_t shift = align64(w1);
+        for (size_t u = second; u < nodes.size(); ++u) {
+          c->node_off[u] += shift;
+          if (!nodes[u].is_leaf) ws = std::max<int64_t>(ws, c->node_off[u] + (int64_t)nodes[u].out_card);
+        }
+        c->pair_u[0] = up;
+        c->pair_u[1] = uq;
+      }
+    }
   }
   // leaf that folds the core: the smallest Y (ties: lowest mode)
   for (int n = 0; n < N; ++n) {
@@ -491,12 +576,31 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   // ---- eigensolver jobs
   size_t work = 0;
   c->jobs_h.resize(N);
+  std::vector<EigFullJob> fjobs(N);
+  size_t fwork = 0;
+  for (int n = 0; n < N; ++n) {
+    c->full_only[n] = s.K[n] > eig_max_K();
+    EigFullJob& f = fjobs[n];
+    f.L = (int)s.L[n];
+    f.K = (int)s.K[n];
+    f.status_idx = n;
+    f.only_if_failed = c->full_only[n] ? 0 : 1;
+    f.S_off = (int64_t)c->sofs[n];
+    f.F_off = (int64_t)c->fofs[n];
+    f.ev_off = (int64_t)c->kofs[n];
+    f.work_off = (int64_t)fwork;
+    fwork += eig_full_work_elems(f.L);
+    c->fLmax = std::max(c->fLmax, f.L);
+    c->fKmax = std::max(c->fKmax, f.K);
+  }
   for (int n = 0; n < N; ++n) {
     EigJob& j = c->jobs_h[n];
     const int64_t rank_bound = (int64_t)(s.card(((1u << N) - 1) & ~(1u << n)) / s.L[n]);
     j.L = (int)s.L[n];
     j.K = (int)s.K[n];
-    j.p = eig_block_size(j.L, j.K, rank_bound);
+    // full-only modes never run the subspace kernel; a small block keeps the
+    // shared block width and work areas of the others unchanged
+    j.p = c->full_only[n] ? 8 : eig_block_size(j.L, j.K, rank_bound);
     j.pad_ = 0;
     j.S_off = (int64_t)c->sofs[n];
     j.V0_off = (int64_t)c->fofs[n];
@@ -561,6 +665,8 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   if ((rc = dalloc((void**)&c->status, sizeof(int) * 2 * N))) return bail(rc);
   if ((rc = dalloc((void**)&c->jobs, sizeof(EigJob) * N))) return bail(rc);
   if ((rc = dalloc((void**)&c->jobs_cold, sizeof(EigJob) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->fjobs, sizeof(EigFullJob) * N))) return bail(rc);
+  if ((rc = dalloc((void**)&c->fwork, sizeof(double) * fwork))) return bail(rc);
   if ((rc = dalloc((void**)&c->gpart, sizeof(double) * c->gpart_elems))) return bail(rc);
   if ((rc = dalloc((void**)&c->rpart, sizeof(double) * sumsq_partials()))) return bail(rc);
   if ((rc = ensure_scal(c, 64))) return bail(rc);
@@ -617,6 +723,9 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
                                   hipMemcpyHostToDevice, c->st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->jobs_cold, cold.data(), sizeof(EigJob) * N, hipMemcpyHostToDevice,
+                         c->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->fjobs, fjobs.data(), sizeof(EigFullJob) * N, hipMemcpyHostToDevice,
                          c->st);
     if (e != hipSuccess) {
       delete c;
@@ -676,6 +785,116 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   return TK_OK;
 }
 
+namespace {
+int eig_solve(int count, int L, int K, const double* S, const double* V0, double* F,
+              double* evals, hipStream_t st, bool full_only);
+}  // namespace
+
+// STHOSVD start (Sec. 1, Sec. 2.2): modes in `order`, each taking the leading
+// K_n eigenvectors of the Gram of the current tensor's mode-n unfolding and
+// truncating the tensor along n before the next mode.  The factors then seed
+// an ordinary context.
+extern "C" int hooi_init_sthosvd(int N, const int64_t* L, const int64_t* K, int tdtype,
+                                 const void* T_dev, const tk_plan* plan, int compute,
+                                 const int* order, void* stream, tk_ctx** out) {
+  clear_error();
+  if (!out) return fail(TK_EINVAL, "out is null");
+  *out = nullptr;
+  Shape s;
+  if (int rc = make_shape(N, L, K, &s)) return rc;
+  if (!T_dev) return fail(TK_EINVAL, "T_dev is null");
+  if (tdtype < TK_F64 || tdtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
+    return fail(TK_EINVAL, "unknown compute mode %d", compute);
+  if ((tdtype == TK_F64) != (compute == TK_C_FP64))
+    return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
+  const int maxL = std::min(compute == TK_C_FP64 ? 512 : ttm_max_L(), eig_full_max_L());
+  for (int j = 0; j < N; ++j)
+    if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
+  int ord[TK_MAX_MODES];
+  bool seen[TK_MAX_MODES] = {};
+  for (int i = 0; i < N; ++i) {
+    ord[i] = order ? order[i] : i;
+    if (ord[i] < 0 || ord[i] >= N || seen[ord[i]])
+      return fail(TK_EINVAL, "order is not a permutation of the modes");
+    seen[ord[i]] = true;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // the truncations run at FP64 for FP64 storage, else at FP32 (FP32 or BF16 input)
+  const int wdt = tdtype == TK_F64 ? TK_F64 : TK_F32;
+  const int tcomp = tdtype == TK_F64 ? TK_C_FP64 : TK_C_FP32;
+  const size_t wsz = dtype_size(wdt);
+  size_t fofs[TK_MAX_MODES + 1] = {};
+  for (int n = 0; n < N; ++n) fofs[n + 1] = fofs[n] + (size_t)(s.L[n] * s.K[n]);
+  int64_t Lmax = 0, Kmax = 0;
+  size_t gp = 0, ymax = 0;
+  uint32_t pre = 0;
+  for (int i = 0; i < N; ++i) {
+    const int n = ord[i];
+    Lmax = std::max(Lmax, s.L[n]);
+    Kmax = std::max(Kmax, s.K[n]);
+    gp = std::max(gp, gram_workspace_elems(s.L[n], (int64_t)(s.card(pre) / s.L[n])));
+    pre |= 1u << n;
+    if (i + 1 < N) ymax = std::max(ymax, (size_t)s.card(pre));
+  }
+  double *F64 = nullptr, *S = nullptr, *ev = nullptr, *part = nullptr;
+  void *ya = nullptr, *yb = nullptr, *Fw = nullptr;
+  auto cleanup = [&]() {
+    for (void* q : {(void*)F64, (void*)S, (void*)ev, (void*)part, ya, yb, Fw})
+      if (q) (void)hipFree(q);
+  };
+  int rc = TK_OK;
+  if ((rc = dalloc((void**)&F64, sizeof(double) * fofs[N])) ||
+      (rc = dalloc((void**)&S, sizeof(double) * Lmax * Lmax)) ||
+      (rc = dalloc((void**)&ev, sizeof(double) * Kmax)) ||
+      (rc = dalloc((void**)&part, sizeof(double) * gp)) ||
+      (ymax > 0 && ((rc = dalloc(&ya, wsz * ymax)) || (rc = dalloc(&yb, wsz * ymax)))) ||
+      (wdt == TK_F32 && (rc = dalloc(&Fw, sizeof(float) * Lmax * Kmax)))) {
+    cleanup();
+    return rc;
+  }
+  const void* Y = T_dev;
+  int ydt = tdtype;
+  pre = 0;
+  for (int i = 0; i < N; ++i) {
+    const int n = ord[i];
+    int64_t A, Ln, B;
+    view(s, pre, n, &A, &Ln, &B);
+    hipError_t e = launch_gram(ydt, Y, A, Ln, B, S, part, st);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(TK_EDEVICE, "STHOSVD Gram failed: %s", hipGetErrorString(e));
+    }
+    // synchronises; subspace iteration first, the gap-free solver if needed
+    if ((rc = eig_solve(1, (int)Ln, (int)s.K[n], S, nullptr, F64 + fofs[n], ev, st, false))) {
+      cleanup();
+      return rc;
+    }
+    if (i + 1 == N) break;  // the last truncation would only form the core
+    const void* Fn = F64 + fofs[n];
+    if (wdt == TK_F32) {
+      e = launch_convert(TK_F64, TK_F32, F64 + fofs[n], Fw, Ln * s.K[n], st);
+      Fn = Fw;
+    }
+    void* Ynext = (i % 2 == 0) ? ya : yb;
+    if (e == hipSuccess)
+      e = launch_ttm(ydt, tcomp, Y, A, Ln, B, Fn, s.K[n], Ynext, st, true);
+    if (e != hipSuccess) {
+      cleanup();
+      return fail(TK_EDEVICE, "STHOSVD truncation failed: %s", hipGetErrorString(e));
+    }
+    Y = Ynext;
+    ydt = wdt;
+    pre |= 1u << n;
+  }
+  std::vector<double> Fh(fofs[N]);
+  hipError_t e = hipMemcpyAsync(Fh.data(), F64, sizeof(double) * fofs[N], hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  cleanup();
+  if (e != hipSuccess) return fail(TK_EDEVICE, "STHOSVD readback failed: %s", hipGetErrorString(e));
+  return hooi_init(N, L, K, tdtype, T_dev, plan, compute, Fh.data(), stream, out);
+}
+
 extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
   clear_error();
   if (!c) return fail(TK_EINVAL, "ctx is null");
@@ -692,7 +911,15 @@ extern "C" int hooi_iterate(tk_ctx* c, int iters, double* rel_err) {
   std::vector<double> g2(iters + 1);
   TK_HIP(hipMemcpyAsync(g2.data(), c->scal + 1, sizeof(double) * (iters + 1), hipMemcpyDeviceToHost,
                         c->st));
-  if (int rc = check_status(c)) return rc;  // synchronises
+  if (int rc = check_status(c)) {  // synchronises
+    // keep the factors the last pass started from (each was produced by a
+    // converged solve) instead of adopting the failed update; the core of
+    // that decomposition is formed again on demand
+    std::swap(c->F64a, c->F64b);
+    std::swap(c->Fc, c->Fcb);
+    c->core_valid = false;
+    return rc;
+  }
   for (int t = 0; t < iters; ++t)
     if (rel_err) rel_err[t] = rel_err_of(c->normT2, g2[t + 1]);
   c->normG2 = g2[iters];
@@ -959,6 +1186,22 @@ extern "C" int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   return TK_OK;
 }
 
+extern "C" int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp,
+                           int64_t M, int64_t Lq, int64_t B, const void* Fp, int64_t Kp,
+                           const void* Fq, int64_t Kq, void* outp, void* outq, void* stream) {
+  clear_error();
+  if (!in || !Fp || !Fq || !outp || !outq) return fail(TK_EINVAL, "null pointer");
+  if (A < 1 || Lp < 1 || M < 1 || Lq < 1 || B < 1 || Kp < 1 || Kq < 1 || Kp > Lp || Kq > Lq)
+    return fail(TK_EINVAL, "bad sizes");
+  if (!ttm_pair_applies(in_dtype, compute, in, A, Lp, M, Lq, B, Kp, Kq, outp, outq))
+    return fail(TK_EUNSUPPORTED,
+                "fused pair needs FP32 input and compute, B %% 4 == 0, Lq <= 256, K <= 20, "
+                "16-byte aligned buffers and at least 2048 tiles of four columns");
+  TK_HIP(launch_ttm_pair((const float*)in, A, Lp, M, Lq, B, (const float*)Fp, Kp,
+                         (const float*)Fq, Kq, (float*)outp, (float*)outq, (hipStream_t)stream));
+  return TK_OK;
+}
+
 extern "C" int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
                        void* stream) {
   clear_error();
@@ -976,52 +1219,91 @@ extern "C" int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_
   return TK_OK;
 }
 
-extern "C" int tk_eig_leading(int count, int L, int K, const double* S, const double* V0, double* F,
-                              double* evals, void* stream) {
-  clear_error();
+namespace {
+
+// count matrices: subspace iteration (unless full_only or K above its block
+// limit), then the gap-free solver for every matrix that needs it.
+int eig_solve(int count, int L, int K, const double* S, const double* V0, double* F,
+              double* evals, hipStream_t st, bool full_only) {
   if (!S || !F || !evals) return fail(TK_EINVAL, "null pointer");
   if (count < 1 || L < 1 || K < 1 || K > L) return fail(TK_EINVAL, "bad sizes");
-  if (L > 1024 || K > eig_max_K()) return fail(TK_EUNSUPPORTED, "L <= 1024 and K <= %d required", eig_max_K());
-  hipStream_t st = (hipStream_t)stream;
+  if (L > eig_full_max_L()) return fail(TK_EUNSUPPORTED, "L <= %d required", eig_full_max_L());
+  const bool subspace = !full_only && K <= eig_max_K() && L <= 1024;
   const int p = eig_block_size(L, K, L);
-  std::vector<EigJob> jobs(count);
+  std::vector<EigJob> jobs(subspace ? count : 0);
+  std::vector<EigFullJob> fjobs(count);
   for (int m = 0; m < count; ++m) {
-    EigJob& j = jobs[m];
-    j.L = L;
-    j.K = K;
-    j.p = p;
-    j.pad_ = 0;
-    j.S_off = (int64_t)m * L * L;
-    j.V0_off = V0 ? (int64_t)m * L * K : -1;
-    j.F_off = (int64_t)m * L * K;
-    j.ev_off = (int64_t)m * K;
-    j.work_off = (int64_t)(m * eig_work_elems(L, p));
+    if (subspace) {
+      EigJob& j = jobs[m];
+      j.L = L;
+      j.K = K;
+      j.p = p;
+      j.pad_ = 0;
+      j.S_off = (int64_t)m * L * L;
+      j.V0_off = V0 ? (int64_t)m * L * K : -1;
+      j.F_off = (int64_t)m * L * K;
+      j.ev_off = (int64_t)m * K;
+      j.work_off = (int64_t)(m * eig_work_elems(L, p));
+    }
+    EigFullJob& f = fjobs[m];
+    f.L = L;
+    f.K = K;
+    f.status_idx = m;
+    f.only_if_failed = subspace ? 1 : 0;
+    f.S_off = (int64_t)m * L * L;
+    f.F_off = (int64_t)m * L * K;
+    f.ev_off = (int64_t)m * K;
+    f.work_off = (int64_t)(m * eig_full_work_elems(L));
   }
   EigJob* jd = nullptr;
-  double* work = nullptr;
+  EigFullJob* fd = nullptr;
+  double *work = nullptr, *fwork = nullptr;
   int* status = nullptr;
   int rc = TK_OK;
-  if ((rc = dalloc((void**)&jd, sizeof(EigJob) * count))) return rc;
-  if ((rc = dalloc((void**)&work, sizeof(double) * eig_work_elems(L, p) * count)) ||
+  auto cleanup = [&]() {
+    for (void* q : {(void*)jd, (void*)fd, (void*)work, (void*)fwork, (void*)status})
+      if (q) (void)hipFree(q);
+  };
+  if ((subspace && ((rc = dalloc((void**)&jd, sizeof(EigJob) * count)) ||
+                    (rc = dalloc((void**)&work, sizeof(double) * eig_work_elems(L, p) * count)))) ||
+      (rc = dalloc((void**)&fd, sizeof(EigFullJob) * count)) ||
+      (rc = dalloc((void**)&fwork, sizeof(double) * eig_full_work_elems(L) * count)) ||
       (rc = dalloc((void**)&status, sizeof(int) * count))) {
-    (void)hipFree(jd);
-    if (work) (void)hipFree(work);
+    cleanup();
     return rc;
   }
   std::vector<int> sth(count, 0);
-  hipError_t e = hipMemcpyAsync(jd, jobs.data(), sizeof(EigJob) * count, hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(fd, fjobs.data(), sizeof(EigFullJob) * count,
+                                hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = launch_fill_int(status, count, 0, st);
-  if (e == hipSuccess)
-    e = launch_eig(count, jd, 0, L, p, S, V0, F, evals, work, status, nullptr, V0 ? 20 : 100,
-                   1e-11, st);
+  if (subspace) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(jd, jobs.data(), sizeof(EigJob) * count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = launch_eig(count, jd, 0, L, p, S, V0, F, evals, work, status, nullptr, V0 ? 20 : 100,
+                     1e-11, st);
+  }
+  if (e == hipSuccess) e = launch_eig_full(count, fd, L, K, S, F, evals, fwork, status, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(sth.data(), status, sizeof(int) * count, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(jd);
-  (void)hipFree(work);
-  (void)hipFree(status);
+  cleanup();
   if (e != hipSuccess) return fail(TK_EDEVICE, "eig: %s", hipGetErrorString(e));
   for (int m = 0; m < count; ++m)
     if (sth[m] != 0) return fail(TK_ENUMERIC, "eigensolver status %d for matrix %d", sth[m], m);
   return TK_OK;
+}
+
+}  // namespace
+
+extern "C" int tk_eig_leading(int count, int L, int K, const double* S, const double* V0, double* F,
+                              double* evals, void* stream) {
+  clear_error();
+  return eig_solve(count, L, K, S, V0, F, evals, (hipStream_t)stream, false);
+}
+
+extern "C" int tk_eig_full(int count, int L, int K, const double* S, double* F, double* evals,
+                           void* stream) {
+  clear_error();
+  return eig_solve(count, L, K, S, nullptr, F, evals, (hipStream_t)stream, true);
 }

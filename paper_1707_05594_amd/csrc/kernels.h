@@ -21,6 +21,16 @@ bool ttm_bf16_output_ok(int in_dtype, int compute, const void* in, int64_t A, in
                         int64_t B, const void* out, int tile);
 int ttm_max_L();
 
+// Both root TTMs in one pass (ttm2.hip): In viewed as [A, Lp, M, Lq, B],
+// Outp = In x_p Fp^T ([A, Kp, M, Lq, B]) and Outq = In x_q Fq^T ([A, Lp, M, Kq, B]).
+// FP32 input and compute; applies when ttm_pair_applies() holds.
+bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp,
+                      int64_t M, int64_t Lq, int64_t B, int64_t Kp, int64_t Kq,
+                      const void* outp, const void* outq);
+hipError_t launch_ttm_pair(const float* in, int64_t A, int64_t Lp, int64_t M, int64_t Lq,
+                           int64_t B, const float* Fp, int64_t Kp, const float* Fq, int64_t Kq,
+                           float* outp, float* outq, hipStream_t st);
+
 // Grouped TTM (batched HOOI): one descriptor per node, FP32 factor and output.
 enum {
   kGroupedTile = 0,
@@ -109,6 +119,23 @@ void eig_identity_bases(const std::vector<EigJob>& jobs, std::vector<double>* ou
 int eig_block_size(int L, int K, int64_t rank_bound);
 size_t eig_work_elems(int L, int p);  // global work doubles one job may need
 int eig_max_K();
+
+// Gap-free leading eigenpairs (eigfull.hip): Householder tridiagonalisation,
+// implicit QL with eigenvector accumulation, back-transformation of the K
+// largest, sign rule.  One job per matrix; status[status_idx] receives 0
+// (solved), 1 (QL did not converge) or 2 (non-finite); with only_if_failed
+// the job runs only when that word is 1 on entry (a subspace solve before it
+// failed) and otherwise leaves F and ev untouched.  Work: eig_full_work_elems(L)
+// doubles per job at work_base + work_off.  L <= eig_full_max_L().
+struct EigFullJob {
+  int L, K, status_idx, only_if_failed;
+  int64_t S_off, F_off, ev_off, work_off;
+};
+hipError_t launch_eig_full(int count, const EigFullJob* jobs_dev, int Lmax, int Kmax,
+                           const double* S_base, double* F_base, double* ev_base,
+                           double* work_base, int* status, hipStream_t st);
+size_t eig_full_work_elems(int L);
+int eig_full_max_L();
 
 // misc.hip
 hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* part, double* out,

@@ -98,9 +98,14 @@ def test_batch_real_shapes_match_oracle(dtype):
     Bars: HOSVD subspaces 1e-8; after three invocations subspaces 1e-4 (FP32
     leaves, planted gap); the oracle's FP64 explicit residual of the GPU's
     factors (with their optimal core) within 1e-6 relative of the oracle's
-    own error (the error is stationary in the factors); the engine's
-    per-invocation errors within 1e-2 relative (identity error with an FP32
-    core at e ~ 1e-3)."""
+    own error (the error is stationary in the factors).  The engine's
+    per-invocation errors come from the identity e^2 = 1 - ||G||^2 / ||T||^2
+    with an FP32 core of |G| entries; the rounding of the chain that forms it
+    (about u sqrt(sum L) per entry, u = 2^-24, independent between entries)
+    moves ||G||^2 / ||T||^2 by about 2 u sqrt(sum L) / sqrt(|G|), i.e. e by
+    u sqrt(sum L) / (sqrt(|G|) e^2) relative: 9% for an 80-entry core at
+    e = 1e-3, under 1% for the larger ones.  They are checked within four
+    times that figure (the explicit residual is the precise value)."""
     pick, shapes, host, devs = _real_shape_sample(16, dtype)
     print(f"{dtype} sample {pick}: {shapes}", flush=True)
     b = tk.Batch(devs, [K for _, K in shapes])
@@ -121,9 +126,10 @@ def test_batch_real_shapes_match_oracle(dtype):
               f"{e_g:.9e}, engine {cur[i]:.9e}, subspace distance {dist:.2e}", flush=True)
         assert dist < 1e-4, pick[i]
         assert abs(e_g - eo[-1]) < 1e-6 * eo[-1], pick[i]
+        noise = 2.0 ** -24 * np.sqrt(sum(L)) / (np.sqrt(np.prod(K)) * eo[-1] ** 2)
         for t in range(1, iters):
-            assert abs(errs[t, i] - eo[t - 1]) < 1e-2 * eo[t - 1], (pick[i], t)
-        assert abs(cur[i] - eo[-1]) < 1e-2 * eo[-1], pick[i]
+            assert abs(errs[t, i] - eo[t - 1]) < 4 * noise * eo[t - 1], (pick[i], t, noise)
+        assert abs(cur[i] - eo[-1]) < 4 * noise * eo[-1], (pick[i], noise)
 
 
 def test_batch_matches_single_tensor_engine():

@@ -300,3 +300,135 @@ def test_fp32_compute_on_bf16_input_reproduces_24_bit_factors():
     expect = np.float32(8.0 * float(f))
     assert float(expect) == 8.0 * float(f)  # exact in FP32
     np.testing.assert_array_equal(out.cpu().numpy(), np.full((A, K, B), expect, np.float32))
+
+
+def _random_gram(g, L, C):
+    """Gram of an L x C unfolding of a randomly filled tensor (Sec. 6.1 fills
+    its benchmark tensors with random values): a Wishart-like spectrum with no
+    planted gap anywhere."""
+    Y = g.standard_normal((L, C))
+    return Y @ Y.T
+
+
+def _check_eig(S, F, ev, K, tag):
+    """Eigenvalues within 1e-12 of the largest (absolute accuracy of a
+    backward-stable solver), residual ||S F - F diag(ev)|| <= 1e-11 ||S||,
+    orthonormality 1e-12, and each vector against eigh's, sign rule applied,
+    within 1e-12 ||S|| / gap_j (its perturbation bound, gap_j = distance of
+    eigenvalue j to the rest of the spectrum)."""
+    w, V = np.linalg.eigh(S)
+    order = np.argsort(-w, kind="stable")
+    Fr = O.sign_rule(V[:, order[:K]])
+    wr = w[order]
+    nS = float(wr[0]) if wr[0] > 0 else 1.0
+    np.testing.assert_allclose(ev, wr[:K], rtol=0, atol=1e-12 * nS, err_msg=tag)
+    assert np.linalg.norm(S @ F - F * ev) <= 1e-11 * nS, tag
+    assert np.abs(F.T @ F - np.eye(K)).max() <= 1e-12, tag
+    for j in range(K):
+        gap = min([abs(wr[j] - wr[i]) for i in range(len(wr)) if i != j] or [nS])
+        if gap > 1e-6 * nS:
+            err = np.abs(F[:, j] - Fr[:, j]).max()
+            assert err <= 1e-12 * nS / gap + 1e-13, (tag, j, err, gap / nS)
+
+
+@pytest.mark.parametrize("L,ratio", [(1, 1.0), (2, 1.0), (3, 1.5), (65, 1.25), (100, 1.25),
+                                     (200, 2.0), (400, 1.25), (672, 1.25)])
+def test_eig_full_random_gram(L, ratio):
+    """The gap-free solver (tridiagonalisation + implicit QL) on Grams of
+    randomly filled unfoldings with K = L / ratio (the paper's benchmark
+    ranks, Sec. 6.1), against numpy.linalg.eigh."""
+    torch, dev = torch_dev()
+    K = max(1, int(round(L / ratio)))
+    print(f"eig_full L={L} K={K}", flush=True)
+    g = np.random.default_rng(L + 7)
+    count = 2 if L <= 200 else 1
+    S = np.stack([_random_gram(g, L, 2 * L + 3) for _ in range(count)])
+    F, ev = tk.eig_full(to_dev(S), K)
+    torch.cuda.synchronize()
+    F, ev = F.cpu().numpy(), ev.cpu().numpy()
+    for m in range(count):
+        _check_eig(S[m], F[m], ev[m], K, f"L={L} K={K} m={m}")
+
+
+@pytest.mark.parametrize("L,K", [(96, 8), (200, 20), (130, 48), (150, 100)])
+def test_eig_leading_without_gap(L, K):
+    """tk_eig_leading on matrices whose K-th eigenvalue sits in a nearly flat
+    cluster (relative spacing 1e-6) with L > 64: subspace iteration cannot
+    converge there and hands the matrix to the gap-free solver (and K > 48
+    goes there directly); warm starts included.  The cluster makes single
+    vectors undefined, so vectors are checked by residual and orthonormality
+    and the K-dimensional subspace is compared only through the residual."""
+    torch, dev = torch_dev()
+    print(f"eig without gap L={L} K={K}", flush=True)
+    g = np.random.default_rng(L * 5 + K)
+    S = []
+    for _ in range(2):
+        Q, _ = np.linalg.qr(g.standard_normal((L, L)))
+        top = np.sort(g.uniform(10.0, 100.0, K // 2))[::-1]
+        w = np.concatenate([top, 1.0 + 1e-6 * g.uniform(0, 1, L - K // 2)])
+        S.append((Q * w) @ Q.T)
+    S = np.stack(S)
+    starts = [None]
+    if K <= 48:
+        starts.append(np.stack([np.linalg.qr(g.standard_normal((L, K)))[0] for _ in range(2)]))
+    for V0 in starts:
+        F, ev = tk.eig_leading(to_dev(S), K, V0=to_dev(V0) if V0 is not None else None)
+        torch.cuda.synchronize()
+        F, ev = F.cpu().numpy(), ev.cpu().numpy()
+        for m in range(2):
+            wr = np.linalg.eigvalsh(S[m])[::-1][:K]
+            np.testing.assert_allclose(ev[m], wr, rtol=0, atol=1e-12 * wr[0])
+            assert np.linalg.norm(S[m] @ F[m] - F[m] * ev[m]) <= 1e-11 * wr[0]
+            assert np.abs(F[m].T @ F[m] - np.eye(K)).max() <= 1e-12
+            cols = np.arange(K)
+            assert np.all(F[m][np.abs(F[m]).argmax(axis=0), cols] > 0)
+
+
+# (A, Lp, M, Lq, B, Kp, Kq): the fused pass over both root children
+PAIR_CASES = [
+    (2, 37, 64, 200, 64, 20, 20),   # 200-row groups (last wave partly idle), K = 20 twice
+    (3, 9, 240, 67, 12, 7, 13),     # ragged rows and K, short runs of b
+    (1, 24, 512, 256, 16, 20, 1),   # every lane busy, K_q = 1
+    (4096, 2, 1, 1, 4, 1, 1),       # one row: L_q = 1 (K_q = 1), M = 1
+    (1, 64, 40, 48, 400, 8, 12),    # A = 1, wide b
+]
+
+
+@pytest.mark.parametrize("A,Lp,M,Lq,B,Kp,Kq", PAIR_CASES)
+def test_ttm_pair_fp32(A, Lp, M, Lq, B, Kp, Kq):
+    """Both root TTMs from one pass: each output element-wise against the
+    oracle's TTM of the same input along p and along q (bound (L + 2) 2^-24
+    of the magnitude bound), and bitwise repeatable."""
+    torch, dev = torch_dev()
+    print(f"ttm pair A={A} Lp={Lp} M={M} Lq={Lq} B={B} Kp={Kp} Kq={Kq}", flush=True)
+    g = np.random.default_rng(A + Lp + M + Lq + B + Kp + Kq)
+    X = g.standard_normal((A, Lp, M, Lq, B)).astype(np.float32)
+    Fp = g.standard_normal((Lp, Kp)).astype(np.float32)
+    Fq = g.standard_normal((Lq, Kq)).astype(np.float32)
+    xd = to_dev(X)
+    op = torch.full((A, Kp, M, Lq, B), float("nan"), dtype=torch.float32, device=dev)
+    oq = torch.full((A, Lp, M, Kq, B), float("nan"), dtype=torch.float32, device=dev)
+    tk.ttm_pair(xd, A, Lp, M, Lq, B, to_dev(Fp), Kp, to_dev(Fq), Kq, op, oq)
+    torch.cuda.synchronize()
+    X64 = X.astype(np.float64)
+    Fp64, Fq64 = Fp.astype(np.float64), Fq.astype(np.float64)
+    gp, gq = op.cpu().numpy(), oq.cpu().numpy()
+    assert_elementwise(gp, O.ttm(X64, Fp64.T, 1), abs_ttm(X64, Fp64.T, 1), ttm_tol(Lp, "fp32"),
+                       "pair: mode p")
+    assert_elementwise(gq, O.ttm(X64, Fq64.T, 3), abs_ttm(X64, Fq64.T, 3), ttm_tol(Lq, "fp32"),
+                       "pair: mode q")
+    op2, oq2 = torch.empty_like(op), torch.empty_like(oq)
+    tk.ttm_pair(xd, A, Lp, M, Lq, B, to_dev(Fp), Kp, to_dev(Fq), Kq, op2, oq2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(op2.cpu().numpy(), gp)
+    np.testing.assert_array_equal(oq2.cpu().numpy(), gq)
+
+
+def test_ttm_pair_rejects_unsupported():
+    torch, dev = torch_dev()
+    X = torch.zeros((1, 4, 8, 4, 6), dtype=torch.float32, device=dev)
+    F = torch.zeros((4, 2), dtype=torch.float32, device=dev)
+    o = torch.zeros(1024, dtype=torch.float32, device=dev)
+    with pytest.raises(tk.TuckerError) as e:  # B % 4 != 0 and too few tiles
+        tk.ttm_pair(X, 1, 4, 8, 4, 6, F, 2, F, 2, o, o)
+    assert e.value.code == tk.TK_EUNSUPPORTED
