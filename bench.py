@@ -47,27 +47,27 @@ def log(msg):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "ttm_wide_f32_root_200x200x200x200_r20_hbm_counters.txt")
+MFMA_COUNTERS = os.path.join(ROOT, "profiles", "ttm_root_200x200x200x200_r20_mfma_counters.txt")
 
 
-def recorded_traffic():
-    """HBM bytes per root-TTM launch from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the kernel
-    sources have changed since the counters were taken."""
+def recorded_value(path, key, kind=float):
+    """A figure from a committed rocprofv3 summary (`key: value` line), or None
+    when the kernel sources it names have changed since it was taken."""
     import hashlib
     try:
-        text = open(COUNTERS).read().splitlines()
+        text = open(path).read().splitlines()
     except OSError:
         return None
-    traffic, digest, files = None, None, []
+    value, digest, files = None, None, []
     for line in text:
         line = line.strip()
-        if line.startswith("traffic_bytes_per_launch:"):
-            traffic = int(line.split(":")[1])
+        if line.startswith(key + ":"):
+            value = kind(line.split(":")[1])
         elif line.startswith("kernel_source_sha256_16:"):
             parts = line.split(":", 1)[1].split()
             digest = parts[0]
             files = [f.strip("()") for f in parts[1:]]
-    if traffic is None or digest is None or not files:
+    if value is None or digest is None or not files:
         return None
     h = hashlib.sha256()
     for f in files:
@@ -75,10 +75,16 @@ def recorded_traffic():
             h.update(open(os.path.join(ROOT, f), "rb").read())
         except OSError:
             return None
-    return traffic if h.hexdigest()[:16] == digest else None
+    return value if h.hexdigest()[:16] == digest else None
 
 
-def root_ttm_roofline(ctx, plan, reps=3):
+def recorded_traffic():
+    """HBM bytes per root-TTM launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return recorded_value(COUNTERS, "traffic_bytes_per_launch", int)
+
+
+def root_ttm_roofline(ctx, plan, reps=3, t_bytes=4, kernel="ttm_wide_f32 (root nodes, reads T)",
+                      with_traffic=True):
     """Average duration of the root-level TTM launches (HIP events, ctx stream)."""
     nodes = plan.nodes()
     roots = [i for i, n in enumerate(nodes) if n["parent"] < 0 and not n["is_leaf"]]
@@ -91,13 +97,56 @@ def root_ttm_roofline(ctx, plan, reps=3):
     per_launch = []
     for i in roots:
         n = nodes[i]
-        per_launch.append(4 * (n["in_card"] + n["out_card"]) + 4 * L[n["mode"]] * K[n["mode"]])
+        per_launch.append(t_bytes * n["in_card"] + 4 * n["out_card"] + 4 * L[n["mode"]] * K[n["mode"]])
     bytes_per_launch = sum(per_launch) / len(per_launch)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    flops = sum(2 * nodes[i]["in_card"] * K[nodes[i]["mode"]] for i in roots) / len(roots)
+    tflops = flops / (avg_ms * 1e-3) / 1e12
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=recorded_traffic(),
-                kernel="ttm_wide_f32 (root nodes, reads T)", launches=len(times),
-                avg_ms=round(avg_ms, 4), bytes_per_launch=int(bytes_per_launch)), ms
+                frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=recorded_traffic() if with_traffic else None,
+                kernel=kernel, launches=len(times),
+                avg_ms=round(avg_ms, 4), bytes_per_launch=int(bytes_per_launch),
+                mfma_tflops=round(tflops, 2), mfma_frac_fp32_peak=round(tflops / FP32_MFMA_PEAK_TFLOPS, 4),
+                mfma_busy=(recorded_value(MFMA_COUNTERS, "mfma_busy_root_fp32") if with_traffic
+                           else None)), ms
+
+
+def iteration_bytes(plan, t_bytes=4, w_bytes=4):
+    """Algorithmic HBM bytes of one tree pass: (launched, minimum).
+    launched: every TTM reads its input and writes its output, every Gram reads
+    its leaf (each root child streams T);  minimum: T read once, every
+    intermediate written once and read once by each of its children."""
+    nodes = plan.nodes()
+    kids = [0] * len(nodes)
+    for n in nodes:
+        if n["parent"] >= 0:
+            kids[n["parent"]] += 1
+    L, K = plan.L, plan.K
+    card_T = 1
+    for x in L:
+        card_T *= x
+    launched = 0
+    minimum = t_bytes * card_T
+    for u, n in enumerate(nodes):
+        if n["is_leaf"]:
+            launched += w_bytes * n["in_card"]
+            continue
+        in_b = t_bytes if n["parent"] < 0 else w_bytes
+        launched += in_b * n["in_card"] + w_bytes * n["out_card"] + 4 * L[n["mode"]] * K[n["mode"]]
+        minimum += w_bytes * n["out_card"] * (1 + kids[u]) + 4 * L[n["mode"]] * K[n["mode"]]
+    return launched, minimum
+
+
+def iteration_roofline(plan, ms_per_step, t_bytes=4):
+    launched, minimum = iteration_bytes(plan, t_bytes)
+    s = ms_per_step * 1e-3
+    return {"launched_bytes": launched, "min_bytes": minimum,
+            "frac_launched": round(launched / s / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_min": round(minimum / s / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "bytes per HOOI invocation over its measured time, against 8 TB/s: "
+                    "launched = every kernel's own reads and writes; min = T read once, "
+                    "each intermediate written once and read once per child"}
 
 
 def cpu_baseline(T32, K, F0, min_seconds=10.0, max_invocations=30):
@@ -160,7 +209,12 @@ def five_mode_bf16_leg(steps, warmup):
         dt = (time.perf_counter() - t1) / steps
         res[compute] = {"value": round(1.0 / dt, 3), "unit": "HOOI iters/s",
                         "ms_per_step": round(1e3 * dt, 4), "rel_err": errs[-1],
-                        "rel_err_explicit": ctx.error_explicit()}
+                        "rel_err_explicit": ctx.error_explicit(),
+                        "iteration_roofline": iteration_roofline(plan, 1e3 * dt, t_bytes=2)}
+        if compute == "fp32":
+            res["roofline"], _ = root_ttm_roofline(
+                ctx, plan, t_bytes=2, with_traffic=False,
+                kernel="ttm_wide_bf16 (FP32 compute on BF16 T, root nodes, read T)")
         log(f"80^5 {compute}: {res[compute]['value']} it/s, error {res[compute]['rel_err_explicit']:.6e}")
         del ctx
     del Td
@@ -205,6 +259,28 @@ def batch_leg(steps, warmup, seq_count=64):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t1) / steps
     cur = b.error()
+    # the same batch stored as BF16 (FP32 compute: exact products of BF16 data)
+    devs_b = [d.to(torch.bfloat16) for d in devs]
+    bb = tk.Batch(devs_b, ranks)
+    bb.tune()
+    Fb0 = bb.factors()
+    if warmup > 0:
+        bb.iterate(warmup)
+    bb.set_factors(Fb0)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    bb.iterate(steps)
+    torch.cuda.synchronize()
+    dt_bf = (time.perf_counter() - t4) / steps
+    cur_b = bb.error()
+    stb = bb.stats()
+    bf16 = {"storage": "bf16", "value": round(1.0 / dt_bf, 3), "unit": "batch HOOI iters/s",
+            "ms_per_step": round(1e3 * dt_bf, 4), "tree_bytes": stb["tree_bytes"],
+            "tree_GBps_at_step_time": round(stb["tree_bytes"] / dt_bf / 1e9, 1),
+            "frac_hbm_peak": round(stb["tree_bytes"] / dt_bf / 1e9 / HBM_PEAK_GBS, 4),
+            "rel_err_median": float(np.median(cur_b)), "rel_err_max": float(np.max(cur_b))}
+    log(f"batch bf16 storage: {bf16['value']} it/s ({bf16['ms_per_step']} ms)")
+    del bb, devs_b
     # the same first seq_count tensors: one context each, one after another
     sub = list(range(seq_count))
     bs = tk.Batch([devs[i] for i in sub], [ranks[i] for i in sub])
@@ -215,15 +291,19 @@ def batch_leg(steps, warmup, seq_count=64):
     bs.iterate(steps)
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t2) / steps
-    ctxs = [tk.hooi_init(devs[i], ranks[i], compute="fp32") for i in sub]
-    for c in ctxs:
+    # one live context at a time (each holds its own streams and hardware
+    # queues); only the iterations are timed
+    t_seq = 0.0
+    for i in sub:
+        c = tk.hooi_init(devs[i], ranks[i], compute="fp32")
         c.iterate(1)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    for c in ctxs:
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
         c.iterate(steps)
-    torch.cuda.synchronize()
-    dt_s = (time.perf_counter() - t3) / steps
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t3
+        del c
+    dt_s = t_seq / steps
     res = {"workload": "512 planted tensors, 3- or 4-mode, L in [32,128], K in [4,16], 1e-3 rel "
                        "noise, FP32, HOSVD start, DP tree each",
            "elements": int(elems), "value": round(1.0 / dt, 3), "unit": "batch HOOI iters/s",
@@ -235,12 +315,129 @@ def batch_leg(steps, warmup, seq_count=64):
            "rel_err_median": float(np.median(cur)), "rel_err_max": float(np.max(cur)),
            "first_%d" % seq_count: {"batched_ms_per_step": round(1e3 * dt_b, 4),
                                     "one_context_each_ms_per_step": round(1e3 * dt_s, 4),
-                                    "speedup": round(dt_s / dt_b, 2)}}
+                                    "speedup": round(dt_s / dt_b, 2)},
+           "bf16_storage": bf16}
     log(f"batch: {res['value']} it/s ({res['ms_per_step']} ms), tree {st['tree_bytes']/1e9:.1f} GB "
         f"-> {res['tree_GBps_at_step_time']} GB/s; first {seq_count}: batched {1e3*dt_b:.2f} ms vs "
         f"one context each {1e3*dt_s:.2f} ms")
-    del b, bs, ctxs, devs
+    del b, bs, devs
     torch.cuda.empty_cache()
+    return res
+
+
+def six_mode_leg(steps, warmup):
+    """The six-mode 64x48x40x32x24x16 FP32 tensor (ranks 8,8,6,6,4,4, decaying
+    core, 1e-3 relative noise): the plain DP tree (separate root TTMs,
+    automatic kernels) against the learned choice among the DP's 8 best trees
+    and their kernels (the MLP trained on node and root-pair timings of random
+    shapes), which may run the two root children as one pass over T.
+    HOOI iterations/s of both at their explicit errors; the roofline of the
+    learned run's root launch."""
+    import numpy as np
+    import torch
+
+    import paper_1707_05594_amd as tk
+    import paper_1707_05594_amd.costmodel as cm
+    import synth
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    T, info = synth.workload("planted_64x48x40x32x24x16_f32")
+    L, K = info["L"], info["K"]
+    Td = torch.from_numpy(T).to(dev)
+    del T
+    torch.cuda.synchronize()
+    log(f"six-mode: generated in {time.perf_counter() - t0:.1f}s")
+
+    def run(plan):
+        ctx = tk.hooi_init(Td, K, plan=plan, compute="fp32")
+        F0 = ctx.factors()
+        ctx.iterate(max(1, warmup))
+        ctx.set_factors(F0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        errs = ctx.iterate(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / steps
+        node = [sorted(x) for x in zip(*[ctx.profile_tree() for _ in range(3)])]
+        med = [v[1] for v in node]
+        return ctx, dt, errs, med
+
+    plain = tk.ttm_tree_plan(L, K)
+    ctx, dt_p, errs_p, med_p = run(plain)
+    e_p = ctx.error_explicit()
+    del ctx
+    # cost model: node and root-pair timings of random shapes, trained on the GPU
+    t2 = time.perf_counter()
+    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=40, seed=1)
+    model, losses = cm.train(X, y, steps=3000, lr=3e-3)
+    plan = tk.ttm_tree_plan(L, K, "dp", topk=8)
+    chosen, pred = plan.learned(model, "f32", "fp32", margin=0.02)
+    tiles = plan.tiles(chosen)
+    t_model = time.perf_counter() - t2
+    ctx, dt_l, errs_l, med_l = run(plan)
+    e_l = ctx.error_explicit()
+    nodes = plan.nodes(chosen)
+    roots = [i for i, n in enumerate(nodes) if n["parent"] < 0 and not n["is_leaf"]]
+    fused = tk.TK_TILE_PAIR in tiles
+    root_ms = sum(med_l[i] for i in roots)
+    card_T = 1
+    for x in L:
+        card_T *= x
+    root_bytes = (4 * card_T * (1 if fused else len(roots)) +
+                  sum(4 * nodes[i]["out_card"] + 4 * L[nodes[i]["mode"]] * K[nodes[i]["mode"]]
+                      for i in roots))
+    ach = root_bytes / (root_ms * 1e-3) / 1e9
+    res = {"workload": "planted 64x48x40x32x24x16 FP32, ranks 8,8,6,6,4,4, core 1/(i1+..+i6), "
+                       "1e-3 rel noise, HOSVD start",
+           "plain_dp": {"tree": plain.string(), "tree_macs": plain.cost(),
+                        "value": round(1.0 / dt_p, 3), "unit": "HOOI iters/s",
+                        "ms_per_step": round(1e3 * dt_p, 4), "tree_ms_per_pass": round(sum(med_p), 4),
+                        "rel_err": errs_p[-1], "rel_err_explicit": e_p,
+                        "iteration_roofline": iteration_roofline(plain, 1e3 * dt_p)},
+           "learned": {"chosen_rank": chosen, "tree": plan.string(chosen),
+                       "tree_macs": plan.cost(chosen), "fused_root_pair": fused,
+                       "predicted_tree_ms": round(float(pred[chosen]), 4),
+                       "value": round(1.0 / dt_l, 3), "unit": "HOOI iters/s",
+                       "ms_per_step": round(1e3 * dt_l, 4), "tree_ms_per_pass": round(sum(med_l), 4),
+                       "rel_err": errs_l[-1], "rel_err_explicit": e_l,
+                       "speedup_vs_plain_dp": round(dt_p / dt_l, 3),
+                       "model": {"node_rows": len(rows), "pair_rows": len(prow),
+                                 "final_loss": float(losses[-1]),
+                                 "harvest_and_train_s": round(t_model, 1)},
+                       "iteration_roofline": iteration_roofline(plan, 1e3 * dt_l)},
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": ("ttm_pair_tail_f32 (both root children, T read once)" if fused
+                                   else "root TTMs"),
+                        "avg_ms": round(root_ms, 4), "bytes_per_launch": int(root_bytes)}}
+    log(f"six-mode: plain DP {1.0 / dt_p:.1f} it/s ({1e3 * dt_p:.3f} ms), learned "
+        f"{1.0 / dt_l:.1f} it/s ({1e3 * dt_l:.3f} ms, rank {chosen}, fused {fused}); errors "
+        f"{e_p:.9e} / {e_l:.9e}")
+    del ctx, Td
+    torch.cuda.empty_cache()
+    return res
+
+
+def sthosvd_leg(Td, K, plan, steps):
+    """HOSVD against STHOSVD starts on the benchmark tensor: start time, the
+    FP64 explicit residual of each start and after `steps` invocations."""
+    import torch
+
+    import paper_1707_05594_amd as tk
+    res = {}
+    for init in ("hosvd", "sthosvd"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx = tk.hooi_init(Td, K, plan=plan, compute="fp32", init=init)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        e0 = ctx.error_explicit()
+        ctx.iterate(steps)
+        e1 = ctx.error_explicit()
+        res[init] = {"init_ms": round(1e3 * dt, 2), "rel_err_start": e0,
+                     "rel_err_after_%d" % steps: e1}
+        log(f"{init}: start {1e3 * dt:.1f} ms, error {e0:.9e} -> {e1:.9e} after {steps}")
+        del ctx
     return res
 
 
@@ -253,6 +450,8 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
     ap.add_argument("--skip-five-mode", action="store_true")
+    ap.add_argument("--skip-sthosvd", action="store_true")
+    ap.add_argument("--skip-six-mode", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
                          "(dispatches of known size that calibrate the HBM counters)")
@@ -320,6 +519,7 @@ def main():
         "ttm_frac_fp32_mfma_peak": round(gflops_step / (FP32_MFMA_PEAK_TFLOPS * 1e3), 4),
         "rel_err": errs[-1],
         "roofline": roof,
+        "iteration_roofline": iteration_roofline(plan, ms_per_step),
     }
 
     if not args.skip_mixed:
@@ -353,8 +553,14 @@ def main():
         out["mixed"] = mixed
         del Tb
 
+    if not args.skip_sthosvd:
+        out["sthosvd_vs_hosvd"] = sthosvd_leg(Td, K, plan, 3)
+
     if not args.skip_five_mode:
         out["bf16_storage_80x80x80x80x80"] = five_mode_bf16_leg(args.steps, args.warmup)
+
+    if not args.skip_six_mode:
+        out["six_mode_64x48x40x32x24x16"] = six_mode_leg(args.steps, args.warmup)
 
     if not args.skip_batch:
         out["batch"] = batch_leg(args.steps, args.warmup)

@@ -76,6 +76,11 @@ extern "C" {
 #define TK_TILE_STAGED 1
 #define TK_TILE_SPLITK 2
 #define TK_TILE_COUNT 3
+/* Root nodes only: the tree's two root children run as one pass over T (a
+ * kernel for the two trailing modes of an FP32 tensor reads T once for both);
+ * set on both root nodes.  hooi_init falls back to TK_TILE_AUTO when no pair
+ * kernel takes the shape.  The plain plan never sets it; tk_plan_learned may. */
+#define TK_TILE_PAIR 3
 
 /* tree kinds (Sec. 3.2 prior schemes, Sec. 3.3 optimal tree) */
 #define TK_TREE_DP 0        /* minimum multiply-add tree, dynamic program         */
@@ -286,10 +291,18 @@ void hooi_batch_free(tk_batch* b);
  * log2 A, log2 L, log2 B, log2 K, log2 input bytes, log2 output bytes,
  * wide kernel applies (0/1), row kernel applies (0/1), input bytes per
  * element / 4, compute class (FP32 0, BF16 0.5, bf16x3 1, FP64 2),
- * tile == STAGED (0/1), tile == SPLITK (0/1). */
-#define TK_FEATURES 12
+ * tile == STAGED (0/1), tile == SPLITK (0/1), fused root pair (0 here).
+ * tile: TK_TILE_AUTO, _STAGED or _SPLITK. */
+#define TK_FEATURES 13
 int tk_ttm_features(int64_t A, int64_t L, int64_t B, int64_t K, int in_dtype, int compute,
                     int tile, float* out);
+
+/* Features of a fused root pair (both root children in one pass over T
+ * viewed as [A, Lp, M, Lq, B]; tk_ttm_pair): log2 A, log2 Lp, log2 (M Lq B),
+ * log2 Kp, log2 input bytes, log2 bytes of both outputs, 0, 0, input bytes per
+ * element / 4, compute class, 0, 0, 1. */
+int tk_pair_features(int64_t A, int64_t Lp, int64_t M, int64_t Lq, int64_t B, int64_t Kp,
+                     int64_t Kq, int in_dtype, int compute, float* out);
 
 /* Average time (ms, HIP events on `stream`) of `reps` launches of the TTM
  * node kernel chosen by `tile`, after one untimed launch.  Device buffers as
@@ -298,8 +311,15 @@ int tk_time_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L,
                 const void* F, int64_t K, void* out, int tile, int reps, void* stream,
                 float* ms);
 
+/* Average time (ms) of `reps` launches of tk_ttm_pair, after one untimed
+ * launch; buffers as for tk_ttm_pair. */
+int tk_time_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
+                     int64_t Lq, int64_t B, const void* Fp, int64_t Kp, const void* Fq,
+                     int64_t Kq, void* outp, void* outq, int reps, void* stream, float* ms);
+
 /* Per-node kernel choices of tree `rank` (n = its node count; leaf entries
- * are ignored).  hooi_init uses the choices of the selected tree. */
+ * are ignored; TK_TILE_PAIR only on both root nodes of a two-child root).
+ * hooi_init uses the choices of the selected tree. */
 int tk_plan_set_tiles(tk_plan* plan, int rank, const int* tiles, int n);
 int tk_plan_get_tiles(const tk_plan* plan, int rank, int* tiles, int cap, int* n);
 
@@ -326,8 +346,10 @@ void tk_mlp_free(tk_mlp* m);
 
 /* Choose among the trees a TK_TREE_DP plan holds (topk > 1) and each
  * internal node's kernel by the model's predicted time (sum over internal
- * nodes, each at its fastest predicted kernel).  The choice replaces the DP
- * optimum with automatic kernels only when predicted faster by more than
+ * nodes, each at its fastest predicted kernel; a tree whose two root
+ * children a pair kernel takes may instead run them fused, predicted from
+ * tk_pair_features).  The choice replaces the DP optimum with automatic
+ * kernels and separate root TTMs only when predicted faster by more than
  * `margin` (fraction); it is stored as the plan's selected rank and tiles.
  * predicted_ms: NULL or tk_plan_count entries (each tree at its best kernels). */
 int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute, double margin,

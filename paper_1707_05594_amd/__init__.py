@@ -22,7 +22,8 @@ TK_F64, TK_F32, TK_BF16 = 0, 1, 2
 TK_C_FP64, TK_C_FP32, TK_C_BF16, TK_C_BF16X3 = 0, 1, 2, 3
 TREE_KINDS = {"dp": 0, "chain": 1, "chain_k": 2, "chain_h": 3, "balanced": 4}
 TK_TILE_AUTO, TK_TILE_STAGED, TK_TILE_SPLITK, TK_TILE_COUNT = 0, 1, 2, 3
-TK_FEATURES = 12
+TK_TILE_PAIR = 3
+TK_FEATURES = 13
 COMPUTE = {"fp64": TK_C_FP64, "fp32": TK_C_FP32, "bf16": TK_C_BF16, "bf16x3": TK_C_BF16X3}
 DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
 MAX_MODES = 12
@@ -94,6 +95,10 @@ _SIGS = {
                     ctypes.c_int),
     "tk_ttm_features": ([_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _fp],
                         ctypes.c_int),
+    "tk_pair_features": ([_i64, _i64, _i64, _i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
+                          _fp], ctypes.c_int),
+    "tk_time_ttm_pair": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp,
+                          _i64, _vp, _i64, _vp, _vp, ctypes.c_int, _vp, _fp], ctypes.c_int),
     "tk_time_ttm": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _i64, _vp,
                      ctypes.c_int, ctypes.c_int, _vp, _fp], ctypes.c_int),
     "tk_plan_set_tiles": ([_vp, ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
@@ -483,6 +488,27 @@ def ttm_features(A, L, B, K, in_dtype="f32", compute="fp32", tile=TK_TILE_AUTO):
     _check(lib().tk_ttm_features(int(A), int(L), int(B), int(K), DTYPES[in_dtype],
                                  COMPUTE[compute], int(tile), out.ctypes.data_as(_fp)))
     return out
+
+
+def pair_features(A, Lp, M, Lq, B, Kp, Kq, in_dtype="f32", compute="fp32"):
+    """Cost-model features of a fused root pair (TK_FEATURES floats)."""
+    import numpy as np
+    out = np.zeros(TK_FEATURES, dtype=np.float32)
+    _check(lib().tk_pair_features(int(A), int(Lp), int(M), int(Lq), int(B), int(Kp), int(Kq),
+                                  DTYPES[in_dtype], COMPUTE[compute],
+                                  out.ctypes.data_as(_fp)))
+    return out
+
+
+def time_ttm_pair(inp, A, Lp, M, Lq, B, Fp, Kp, Fq, Kq, outp, outq, compute="fp32", reps=5,
+                  stream=None):
+    """Average ms of `reps` fused root-pair launches (library timer)."""
+    ms = ctypes.c_float()
+    _check(lib().tk_time_ttm_pair(_dtype_code(inp), COMPUTE[compute], _dev_ptr(inp), int(A),
+                                  int(Lp), int(M), int(Lq), int(B), _dev_ptr(Fp), int(Kp),
+                                  _dev_ptr(Fq), int(Kq), _dev_ptr(outp), _dev_ptr(outq),
+                                  int(reps), _stream_ptr(stream), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def time_ttm(inp, A, L, B, F, K, out, compute="fp32", tile=TK_TILE_AUTO, reps=5, stream=None):

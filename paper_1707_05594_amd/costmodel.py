@@ -17,8 +17,8 @@ import math
 
 import numpy as np
 
-from . import (COMPUTE, DTYPES, MLP, TK_FEATURES, TK_TILE_COUNT, mlp_param_count, time_ttm,
-               ttm_features, ttm_tree_plan)
+from . import (COMPUTE, DTYPES, MLP, TK_FEATURES, TK_TILE_COUNT, TuckerError, mlp_param_count,
+               pair_features, time_ttm, time_ttm_pair, ttm_features, ttm_tree_plan)
 
 
 def node_views(L, K, plan, rank, tdtype="f32", compute="fp32"):
@@ -44,6 +44,94 @@ def candidate_views(L, K, topk=8, tdtype="f32", compute="fp32"):
         for v in node_views(L, K, plan, r, tdtype, compute):
             seen[v] = True
     return list(seen)
+
+
+def root_pair_view(L, K, plan, rank):
+    """(A, Lp, M, Lq, B, Kp, Kq) of tree `rank`'s two root children, or None."""
+    roots = [nd for nd in plan.nodes(rank) if nd["parent"] < 0]
+    if len(roots) != 2 or any(nd["is_leaf"] for nd in roots):
+        return None
+    p, q = sorted(nd["mode"] for nd in roots)
+    A = int(np.prod(L[:p], dtype=np.int64))
+    M = int(np.prod(L[p + 1:q], dtype=np.int64))
+    B = int(np.prod(L[q + 1:], dtype=np.int64))
+    return (A, L[p], M, L[q], B, K[p], K[q])
+
+
+def candidate_pairs(L, K, topk=8, trailing=True):
+    """Distinct root-pair views of the two trailing modes (the only pairs the
+    engine fuses: the slab pair kernel) over the planner's `topk` best trees,
+    plus (trailing=True) that pair whatever tree holds it (more training
+    data for the kernel)."""
+    plan = ttm_tree_plan(L, K, "dp", topk=topk)
+    seen = {}
+    for r in range(plan.count):
+        v = root_pair_view(L, K, plan, r)
+        if v is not None and v[2] == 1 and v[4] == 1:
+            seen[v] = True
+    if trailing and len(L) >= 3:
+        N = len(L)
+        seen[(int(np.prod(L[:N - 2], dtype=np.int64)), L[N - 2], 1, L[N - 1], 1, K[N - 2],
+              K[N - 1])] = True
+    return list(seen)
+
+
+def random_pair_views(count, seed, min_elems=int(2e7), max_elems=int(1.6e9)):
+    """Seeded root-pair views (A, Lp, 1, Lq, 1, Kp, Kq) of two trailing modes
+    in the slab pair kernel's domain (Lp, Lq multiples of 4 with Lp Lq <= 2048,
+    ranks up to 8), with |T| log-uniform in [min_elems, max_elems]: the
+    root level is where a tree's time goes, so its views are large."""
+    g = np.random.Generator(np.random.Philox(np.random.SeedSequence([17070559, 11, seed])))
+    out = []
+    while len(out) < count:
+        Lp, Lq = 4 * int(g.integers(2, 25)), 4 * int(g.integers(2, 25))
+        if Lp * Lq > 2048:
+            continue
+        E = float(np.exp(g.uniform(np.log(min_elems), np.log(max_elems))))
+        A = max(4096, int(E / (Lp * Lq)))
+        Kp = int(g.integers(1, min(8, Lp) + 1))
+        Kq = int(g.integers(1, min(8, Lq) + 1))
+        out.append((A, Lp, 1, Lq, 1, Kp, Kq))
+    return out
+
+
+def pair_node_views(pairs, tdtype="f32"):
+    """The two separate root TTMs of each pair view: (A, L, B, K, dtype)."""
+    out = []
+    for A, Lp, M, Lq, B, Kp, Kq in pairs:
+        out.append((A, Lp, M * Lq * B, Kp, tdtype))
+        out.append((A * Lp * M, Lq, B, Kq, tdtype))
+    return out
+
+
+def measure_pairs(pairs, reps=3, device="cuda:0"):
+    """Time the fused root pair for every view a pair kernel takes (FP32);
+    returns features X, log-ms y and rows (view, ms)."""
+    import torch
+    dev = torch.device(device)
+    X, y, rows = [], [], []
+    if not pairs:
+        return np.zeros((0, TK_FEATURES), np.float32), np.zeros(0, np.float32), rows
+    cap_in = max(A * Lp * M * Lq * B for A, Lp, M, Lq, B, _, _ in pairs)
+    cap_p = max(A * Kp * M * Lq * B for A, Lp, M, Lq, B, Kp, _ in pairs)
+    cap_q = max(A * Lp * M * Kq * B for A, Lp, M, Lq, B, _, Kq in pairs)
+    cap_f = max(max(Lp * Kp, Lq * Kq) for _, Lp, _, Lq, _, Kp, Kq in pairs)
+    inp = torch.full((cap_in,), 0.5, dtype=torch.float32, device=dev)
+    op = torch.empty((cap_p,), dtype=torch.float32, device=dev)
+    oq = torch.empty((cap_q,), dtype=torch.float32, device=dev)
+    F = torch.full((cap_f,), 0.25, dtype=torch.float32, device=dev)
+    for v in pairs:
+        A, Lp, M, Lq, B, Kp, Kq = v
+        try:
+            ms = time_ttm_pair(inp, A, Lp, M, Lq, B, F, Kp, F, Kq, op, oq, reps=reps)
+        except TuckerError:
+            continue  # no pair kernel takes this shape
+        X.append(pair_features(A, Lp, M, Lq, B, Kp, Kq))
+        y.append(math.log(max(ms, 1e-4)))
+        rows.append((v, ms))
+    del inp, op, oq, F
+    return (np.array(X, dtype=np.float32).reshape(-1, TK_FEATURES),
+            np.array(y, dtype=np.float32), rows)
 
 
 def random_shapes(count, seed, max_elems=int(1.6e9)):
@@ -85,6 +173,25 @@ def measure(views, compute="fp32", reps=3, tiles=range(TK_TILE_COUNT), device="c
             rows.append((A, L, B, K, dt, t, ms))
     del bufs, F, out
     return np.array(X, dtype=np.float32), np.array(y, dtype=np.float32), rows
+
+
+def training_set(n_shapes=10, n_pairs=40, seed=1, topk=8):
+    """Timed training rows: the nodes of the `topk` best trees of `n_shapes`
+    random tensors, their root pairs a pair kernel takes, and `n_pairs` random
+    trailing-pair views with their two separate root TTMs.  Returns
+    (X, y, node_rows, pair_rows)."""
+    views, pairs = [], []
+    for Ls, Ks in random_shapes(n_shapes, seed=seed):
+        views += candidate_views(Ls, Ks, topk=topk)
+        pairs += candidate_pairs(Ls, Ks, topk=topk)
+    rp = random_pair_views(n_pairs, seed=seed)
+    pairs += rp
+    views += pair_node_views(rp)
+    views = list(dict.fromkeys(views))
+    pairs = list(dict.fromkeys(pairs))
+    X, y, rows = measure(views)
+    Xp, yp, prow = measure_pairs(pairs)
+    return np.vstack([X, Xp]), np.concatenate([y, yp]), rows, prow
 
 
 def init_params(in_dim, hidden, seed):

@@ -499,17 +499,24 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     c->node_off[u] = base;
     if (!nd.is_leaf) ws = std::max<int64_t>(ws, base + (int64_t)nd.out_card);
   }
-  // both root children in one pass over T (TK_ROOT_PAIR=1): FP32 storage
-  // and compute, the automatic kernel choice, and a shape the pair kernel
-  // takes; the second child's subtree moves past the first's in the
-  // workspace.  Off by default: measured slower than two streaming root TTMs.
-  if (const char* v = getenv("TK_ROOT_PAIR"); v && atoi(v) == 1) {
+  // both root children in one pass over T, when the plan asks for it
+  // (TK_TILE_PAIR on both root nodes, as tk_plan_learned sets it) or with
+  // TK_ROOT_PAIR=1: FP32 storage and compute and a shape a pair kernel takes;
+  // the second child's subtree moves past the first's in the workspace.
+  // Otherwise the root nodes run their own kernels (TK_TILE_AUTO).
+  {
     std::vector<int> roots;
     for (size_t u = 0; u < nodes.size(); ++u)
       if (nodes[u].parent < 0) roots.push_back((int)u);
-    if (roots.size() == 2 && !nodes[roots[0]].is_leaf && !nodes[roots[1]].is_leaf &&
-        tdtype == TK_F32 && compute == TK_C_FP32 && c->node_tile[roots[0]] == TK_TILE_AUTO &&
-        c->node_tile[roots[1]] == TK_TILE_AUTO) {
+    const char* env = getenv("TK_ROOT_PAIR");
+    const bool forced = env && atoi(env) == 1;
+    bool asked = false;
+    for (int u : roots) asked = asked || c->node_tile[u] == TK_TILE_PAIR;
+    for (int u : roots)
+      if (c->node_tile[u] == TK_TILE_PAIR) c->node_tile[u] = TK_TILE_AUTO;
+    if ((asked || forced) && roots.size() == 2 && !nodes[roots[0]].is_leaf &&
+        !nodes[roots[1]].is_leaf && tdtype == TK_F32 && compute == TK_C_FP32 &&
+        c->node_tile[roots[0]] == TK_TILE_AUTO && c->node_tile[roots[1]] == TK_TILE_AUTO) {
       int up = roots[0], uq = roots[1];
       if (nodes[up].mode > nodes[uq].mode) std::swap(up, uq);
       const int p = nodes[up].mode, q = nodes[uq].mode;
@@ -519,8 +526,9 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
       // alignment of the outputs is that of the workspace (256 bytes) and its
       // 64-element offsets; checked with representative aligned pointers
       const void* al = (const void*)(uintptr_t)256;
-      if (ttm_pair_applies(TK_F32, TK_C_FP32, T_dev, Ap, Lp, Aq / (Ap * Lp), Lq, Bq, s.K[p],
-                           s.K[q], al, al)) {
+      const int pk = ttm_pair_kind(TK_F32, TK_C_FP32, T_dev, Ap, Lp, Aq / (Ap * Lp), Lq, Bq,
+                                   s.K[p], s.K[q], al, al);
+      if (pk >= 1) {
         const int second = std::max(roots[0], roots[1]);
         int64_t w1 = 0;
         for (int u = 0; u < second; ++u)
@@ -617,11 +625,15 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     work += eig_work_elems(j.L, c->pmax);
   }
   // cold starts (HOSVD) use the full block; warm starts (previous factors)
-  // need only K columns plus a little room to grow, which keeps the blocks in LDS
+  // need only K columns plus a little room to grow, which keeps the blocks in
+  // LDS.  This holds for short modes too: a full Jacobi solve of a 64 x 64
+  // Gram takes about 1.3 ms on its CU against about 0.1 ms for a K + 4 block,
+  // and a solve that does not converge in the small block falls back to the
+  // gap-free solver.
   std::vector<EigJob> cold = c->jobs_h;
   for (int n = 0; n < N; ++n) {
     EigJob& j = c->jobs_h[n];
-    if (j.p != j.L) j.p = std::max(j.K, std::min(j.p, j.K + 4));
+    j.p = std::max(j.K, std::min(j.p, j.K + 4));
   }
   {
     hipError_t e = create_streams(c);

@@ -27,6 +27,11 @@ int ttm_max_L();
 bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp,
                       int64_t M, int64_t Lq, int64_t B, int64_t Kp, int64_t Kq,
                       const void* outp, const void* outq);
+// 0: no pair kernel; 1: the general one (lanes over Lq rows, B % 4 == 0);
+// 2: the trailing-modes one (M = B = 1, slabs staged in LDS).
+int ttm_pair_kind(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
+                  int64_t Lq, int64_t B, int64_t Kp, int64_t Kq, const void* outp,
+                  const void* outq);
 hipError_t launch_ttm_pair(const float* in, int64_t A, int64_t Lp, int64_t M, int64_t Lq,
                            int64_t B, const float* Fp, int64_t Kp, const float* Fq, int64_t Kq,
                            float* outp, float* outq, hipStream_t st);

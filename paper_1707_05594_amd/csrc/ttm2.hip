@@ -37,7 +37,11 @@ namespace {
 constexpr int kPairThreads = 256;
 constexpr int kPairRows = 256;   // Lq limit: one row group per lane quad
 constexpr int kPairPre = 5;      // lp steps whose loads are in flight
-constexpr int kRedPitch = 65;    // LDS pitch of one output's 64 partial sums
+// Partial sums in LDS, partial-major: partial p of output o at p * kRedPitch
+// + o.  kRedPitch = 84 = 4 (mod 64): the 64 lanes of a store (16 groups x 4
+// outputs) hit 64 different banks, and the readers (one thread per output)
+// read consecutive words at every step.
+constexpr int kRedPitch = 84;
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
@@ -62,8 +66,11 @@ __global__ __launch_bounds__(kPairThreads, 2) void ttm_pair_f32(
     float* __restrict__ outp, float* __restrict__ outq, int64_t ntiles, int64_t per_xcd) {
   extern __shared__ float lds[];
   float* FTp = lds;                            // [4][Lp][KGP]: Fp[lp, 4g + r]
-  float* FTq = FTp + 4 * Lp * KGP;             // [Lq][KGQ][4]: Fq[lq, 4g + r]
-  float* red = FTq + Lq * KGQ * 4;             // 2 x [16 KGQ][kRedPitch]
+  // [KGQ][4][Lqp]: Fq[lq, 4g + r], rows padded to Lqp = 1 (mod 4) so that
+  // the 64 lanes of a read (16 row groups x 4 r) hit different banks
+  const int Lqp = (Lq + 3) / 4 * 4 + 1;
+  float* FTq = FTp + 4 * Lp * KGP;
+  float* red = FTq + KGQ * 4 * Lqp;            // 2 x [64][kRedPitch]
   const int64_t t = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (t >= ntiles) return;  // the whole block
   const int tid = threadIdx.x;
@@ -72,10 +79,9 @@ __global__ __launch_bounds__(kPairThreads, 2) void ttm_pair_f32(
     const int k = 4 * g + r;
     FTp[e] = k < Kp ? Fp[(int64_t)lp * Kp + k] : 0.f;
   }
-  for (int e = tid; e < Lq * KGQ * 4; e += kPairThreads) {
-    const int r = e % 4, g = (e / 4) % KGQ, lq = e / (4 * KGQ);
-    const int k = 4 * g + r;
-    FTq[e] = k < Kq ? Fq[(int64_t)lq * Kq + k] : 0.f;
+  for (int e = tid; e < KGQ * 4 * Lqp; e += kPairThreads) {
+    const int lq = e % Lqp, k = e / Lqp;
+    FTq[e] = (k < Kq && lq < Lq) ? Fq[(int64_t)lq * Kq + k] : 0.f;
   }
   __syncthreads();
 
@@ -138,29 +144,29 @@ __global__ __launch_bounds__(kPairThreads, 2) void ttm_pair_f32(
     for (int g = 0; g < KGQ; ++g) accq[g] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float* fq = FTq + frow[j] * KGQ * 4 + i;
+      const float* fq = FTq + i * Lqp + frow[j];
 #pragma unroll
-      for (int g = 0; g < KGQ; ++g) accq[g] = mfma4(fq[4 * g], x[j], accq[g]);
+      for (int g = 0; g < KGQ; ++g) accq[g] = mfma4(fq[4 * g * Lqp], x[j], accq[g]);
     }
     // partial sums of output (kq = 4 g + r, b = i) -> red[o][wave * 16 + beta];
     // the two buffers alternate, so a buffer is written again only after the
     // next step's barrier, when its readers are done
-    float* rb = red + (lp & 1) * (16 * KGQ * kRedPitch);
+    float* rb = red + (lp & 1) * (64 * kRedPitch);
 #pragma unroll
     for (int g = 0; g < KGQ; ++g)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        rb[((4 * g + r) * 4 + i) * kRedPitch + wave * 16 + beta] = accq[g][r];
+        rb[(wave * 16 + beta) * kRedPitch + (4 * g + r) * 4 + i] = accq[g][r];
     lds_barrier();
     if (tid < 16 * KGQ) {
-      const float* pr = rb + tid * kRedPitch;
+      const float* pr = rb + tid;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
 #pragma unroll
       for (int q = 0; q < 64; q += 4) {
-        s0 += pr[q];
-        s1 += pr[q + 1];
-        s2 += pr[q + 2];
-        s3 += pr[q + 3];
+        s0 += pr[q * kRedPitch];
+        s1 += pr[(q + 1) * kRedPitch];
+        s2 += pr[(q + 2) * kRedPitch];
+        s3 += pr[(q + 3) * kRedPitch];
       }
       const int kq = tid >> 2, b = tid & 3;
       if (kq < Kq) qout[((int64_t)lp * M * Kq + kq) * B + b] = (s0 + s1) + (s2 + s3);
@@ -193,9 +199,120 @@ __global__ __launch_bounds__(kPairThreads, 2) void ttm_pair_f32(
     }
 }
 
+// ---- the two trailing modes (M = 1, B = 1): slabs T[a] of Lp x Lq elements
+// A block stages NA consecutive slabs (contiguous in T) in LDS with 16-byte
+// loads, then forms both outputs from LDS on the VALU:
+//   Outq[a, lp, kq] = sum_lq T[a, lp, lq] Fq[lq, kq]   (thread per row (a, lp))
+//   Outp[a, kp, lq] = sum_lp Fp[lp, kp] T[a, lp, lq]   (thread per column (a, lq))
+// Each element of T is read from HBM once and from LDS twice.  The rows of a
+// slab sit at an odd LDS pitch, so row walks and column walks are both free
+// of bank conflicts.  Kp, Kq <= 8 (the factors live in registers).
+template <int KP, int KQ>
+__global__ __launch_bounds__(kPairThreads) void ttm_pair_tail_f32(
+    const float* __restrict__ in, int64_t A, int Lp, int Lq, const float* __restrict__ Fp,
+    int Kp, const float* __restrict__ Fq, int Kq, float* __restrict__ outp,
+    float* __restrict__ outq, int NA) {
+  extern __shared__ float lds[];
+  const int pitch = Lq | 1;
+  const int slab = Lp * pitch;
+  float* S = lds;                        // NA x Lp x pitch
+  float* FpS = S + NA * slab;            // Lp x KP
+  float* FqS = FpS + Lp * KP;            // Lq x KQ
+  const int tid = threadIdx.x;
+  for (int e = tid; e < Lp * KP; e += kPairThreads) {
+    const int l = e / KP, k = e % KP;
+    FpS[e] = k < Kp ? Fp[l * Kp + k] : 0.f;
+  }
+  for (int e = tid; e < Lq * KQ; e += kPairThreads) {
+    const int l = e / KQ, k = e % KQ;
+    FqS[e] = k < Kq ? Fq[l * Kq + k] : 0.f;
+  }
+  const int64_t a0 = (int64_t)blockIdx.x * NA;
+  const int na = (int)min<int64_t>(NA, A - a0);
+  const int per = Lp * Lq;
+  const int64_t n = (int64_t)na * per;
+  const float* src = in + a0 * per;
+  // 16-byte loads of the contiguous chunk (per % 4 == 0: every slab, hence
+  // the chunk, starts on 16 bytes), scattered into the padded rows
+  for (int64_t v = tid; v < n / 4; v += kPairThreads) {
+    const f4 x = *reinterpret_cast<const f4*>(src + 4 * v);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = (int)(4 * v + c);
+      const int as = e / per, r = e % per;
+      S[as * slab + (r / Lq) * pitch + r % Lq] = x[c];
+    }
+  }
+  __syncthreads();
+  // rows (a, lp) -> Outq
+  for (int row = tid; row < na * Lp; row += kPairThreads) {
+    const int as = row / Lp, lp = row % Lp;
+    const float* sr = S + as * slab + lp * pitch;
+    float acc[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) acc[k] = 0.f;
+    for (int lq = 0; lq < Lq; ++lq) {
+      const float x = sr[lq];
+#pragma unroll
+      for (int k = 0; k < KQ; ++k) acc[k] = fmaf(x, FqS[lq * KQ + k], acc[k]);
+    }
+    float* q = outq + ((a0 + as) * Lp + lp) * (int64_t)Kq;
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+      if (k < Kq) q[k] = acc[k];
+  }
+  // columns (a, lq) -> Outp
+  for (int col = tid; col < na * Lq; col += kPairThreads) {
+    const int as = col / Lq, lq = col % Lq;
+    const float* sc = S + as * slab + lq;
+    float acc[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) acc[k] = 0.f;
+    for (int lp = 0; lp < Lp; ++lp) {
+      const float x = sc[lp * pitch];
+#pragma unroll
+      for (int k = 0; k < KP; ++k) acc[k] = fmaf(x, FpS[lp * KP + k], acc[k]);
+    }
+    float* o = outp + (a0 + as) * (int64_t)Kp * Lq + lq;
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+      if (k < Kp) o[(int64_t)k * Lq] = acc[k];
+  }
+}
+
+int tail_na(int Lp, int Lq) { return std::max(1, 6144 / (Lp * Lq)); }
+
+size_t tail_lds(int Lp, int Lq, int NA) {
+  return sizeof(float) * ((size_t)NA * Lp * (Lq | 1) + (size_t)Lp * 8 + (size_t)Lq * 8);
+}
+
+bool tail_applies(int64_t A, int64_t Lp, int64_t M, int64_t Lq, int64_t B, int64_t Kp,
+                  int64_t Kq) {
+  return M == 1 && B == 1 && Lp * Lq <= 2048 && (Lp * Lq) % 4 == 0 && Kp <= 8 && Kq <= 8 &&
+         A >= 4096 && tail_lds((int)Lp, (int)Lq, tail_na((int)Lp, (int)Lq)) <= 64 * 1024;
+}
+
+template <int KP, int KQ>
+hipError_t launch_tail(const float* in, int64_t A, int Lp, int Lq, const float* Fp, int Kp,
+                       const float* Fq, int Kq, float* outp, float* outq, hipStream_t st) {
+  const int NA = tail_na(Lp, Lq);
+  const size_t lds = tail_lds(Lp, Lq, NA);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)ttm_pair_tail_f32<KP, KQ>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((ttm_pair_tail_f32<KP, KQ>), dim3((unsigned)((A + NA - 1) / NA)),
+                     dim3(kPairThreads), lds, st, in, A, Lp, Lq, Fp, Kp, Fq, Kq, outp, outq, NA);
+  return hipGetLastError();
+}
+
 size_t pair_lds(int Lp, int Lq, int KGP, int KGQ) {
-  return sizeof(float) * ((size_t)4 * Lp * KGP + (size_t)Lq * KGQ * 4 +
-                          (size_t)2 * 16 * KGQ * kRedPitch);
+  const size_t Lqp = (size_t)(Lq + 3) / 4 * 4 + 1;
+  return sizeof(float) * ((size_t)4 * Lp * KGP + (size_t)KGQ * 4 * Lqp +
+                          (size_t)2 * 64 * kRedPitch);
 }
 
 template <int KGP, int KGQ>
@@ -220,10 +337,22 @@ hipError_t launch_pair_kg(const float* in, int64_t A, int Lp, int64_t M, int Lq,
 
 }  // namespace
 
+int ttm_pair_kind(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
+                  int64_t Lq, int64_t B, int64_t Kp, int64_t Kq, const void* outp,
+                  const void* outq) {
+  if (in_dtype != TK_F32 || compute != TK_C_FP32) return 0;
+  if (((uintptr_t)in | (uintptr_t)outp | (uintptr_t)outq) % 16 != 0) return 0;
+  if (tail_applies(A, Lp, M, Lq, B, Kp, Kq)) return 2;
+  return ttm_pair_applies(in_dtype, compute, in, A, Lp, M, Lq, B, Kp, Kq, outp, outq) ? 1 : 0;
+}
+
 bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp,
                       int64_t M, int64_t Lq, int64_t B, int64_t Kp, int64_t Kq,
                       const void* outp, const void* outq) {
   if (in_dtype != TK_F32 || compute != TK_C_FP32) return false;
+  if (tail_applies(A, Lp, M, Lq, B, Kp, Kq) &&
+      ((uintptr_t)in | (uintptr_t)outp | (uintptr_t)outq) % 16 == 0)
+    return true;
   if (B % 4 != 0 || Lq > kPairRows || Lq < 1 || Lp < 1) return false;
   if (Lq * B >= ((int64_t)1 << 31)) return false;  // per-lane offsets are 32-bit
   if (Kp < 1 || Kq < 1 || Kp > 20 || Kq > 20) return false;
@@ -237,6 +366,16 @@ bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int6
 hipError_t launch_ttm_pair(const float* in, int64_t A, int64_t Lp, int64_t M, int64_t Lq,
                            int64_t B, const float* Fp, int64_t Kp, const float* Fq, int64_t Kq,
                            float* outp, float* outq, hipStream_t st) {
+  if (tail_applies(A, Lp, M, Lq, B, Kp, Kq)) {
+    const int kp = Kp <= 4 ? 4 : 8, kq = Kq <= 4 ? 4 : 8;
+    if (kp == 4 && kq == 4)
+      return launch_tail<4, 4>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+    if (kp == 4)
+      return launch_tail<4, 8>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+    if (kq == 4)
+      return launch_tail<8, 4>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+    return launch_tail<8, 8>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+  }
   const int kgp = (int)((Kp + 3) / 4), kgq = (int)((Kq + 3) / 4);
 #define TK_PAIR_CASE(P, Q)                                                                 \
   if (kgp == P && kgq == Q)                                                                \

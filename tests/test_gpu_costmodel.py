@@ -4,9 +4,14 @@ six-mode 64x48x40x32x24x16 tensor (ranks 8,8,6,6,4,4).
 
 Bars: forward and loss within 1e-5 relative (FP32 sums of at most 32 terms);
 gradients within 1e-4 normwise (FP32 accumulation over the batch); five Adam
-steps within 1e-3 normwise of the oracle's parameter change.  The selection
-must not be slower than the DP optimum with automatic kernels by more than
-the timing noise (3%)."""
+steps within 1e-3 normwise of the oracle's parameter change.  On the six-mode
+tensor the candidates include running the DP tree's two root children (the
+trailing modes) as one pass over T; the test measures the plain DP tree
+(separate root TTMs, automatic kernels) against the learned choice and asserts
+the learned choice at least 10% faster per HOOI invocation, at the same
+explicit error (1e-6 relative: the same decomposition up to FP32 rounding)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -18,7 +23,7 @@ pytestmark = pytest.mark.gpu
 tk = pytest.importorskip("paper_1707_05594_amd")
 cm = pytest.importorskip("paper_1707_05594_amd.costmodel")
 
-D, H = 12, 32
+D, H = 13, 32
 
 
 def _data(n, seed):
@@ -68,12 +73,11 @@ def test_mlp_adam_steps_match_oracle():
 def test_learned_selection_on_six_mode_tensor():
     torch, dev = torch_dev()
     L, K = (64, 48, 40, 32, 24, 16), (8, 8, 6, 6, 4, 4)
-    # training data: node shapes of the 8 best trees of random tensors (not this one)
-    views = []
-    for Ls, Ks in cm.random_shapes(10, seed=1):
-        views += cm.candidate_views(Ls, Ks, topk=8)
-    print(f"timing {len(views)} node shapes x 3 kernels", flush=True)
-    X, y, _ = cm.measure(views)
+    # training data: node shapes of the 8 best trees of random tensors (not this
+    # one), the root pairs a pair kernel takes, and random trailing-pair views
+    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=40, seed=1)
+    print(f"timed {len(rows)} node rows and {len(prow)} fused root pairs", flush=True)
+    assert len(prow) >= 8
     model, losses = cm.train(X, y, steps=3000, lr=3e-3)
     print(f"training loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
     assert losses[-1] < 0.25 * losses[0]
@@ -89,16 +93,30 @@ def test_learned_selection_on_six_mode_tensor():
     T, _ = synth.workload("planted_64x48x40x32x24x16_f32")
     Td = torch.from_numpy(T).to(dev)
 
-    def tree_ms(rank, tiles=None):
+    def run(rank, tiles=None):
+        """Median tree-pass time (node sum) and HOOI time per invocation (the
+        eigensolves overlap the pass on a side stream), plus the explicit
+        error after the timed invocations."""
         p = tk.ttm_tree_plan(L, K, "dp", topk=8)
         p.select(rank)
         if tiles is not None:
             p.set_tiles(rank, tiles)
         ctx = tk.hooi_init(Td, K, plan=p, compute="fp32")
-        ms = [sum(ctx.profile_tree()) for _ in range(5)]
-        return float(np.median(ms))
+        tree = float(np.median([sum(ctx.profile_tree()) for _ in range(5)]))
+        ctx.iterate(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.iterate(20)
+        torch.cuda.synchronize()
+        it = (time.perf_counter() - t0) / 20 * 1e3
+        return tree, it, ctx.error_explicit()
 
-    t_dp = tree_ms(0)
-    t_learned = tree_ms(chosen, plan.tiles(chosen))
-    print(f"tree time: DP optimum {t_dp:.3f} ms, learned choice {t_learned:.3f} ms", flush=True)
-    assert t_learned <= 1.03 * t_dp
+    tree_dp, it_dp, e_dp = run(0)
+    tree_l, it_l, e_l = run(chosen, plan.tiles(chosen))
+    print(f"DP optimum: tree {tree_dp:.3f} ms, HOOI {it_dp:.3f} ms/invocation, error {e_dp:.9e}",
+          flush=True)
+    print(f"learned (rank {chosen}): tree {tree_l:.3f} ms, HOOI {it_l:.3f} ms/invocation, "
+          f"error {e_l:.9e}; gain {it_dp / it_l:.3f}x", flush=True)
+    assert tk.TK_TILE_PAIR in plan.tiles(chosen)
+    assert it_l <= 0.9 * it_dp
+    assert abs(e_l - e_dp) <= 1e-6 * e_dp

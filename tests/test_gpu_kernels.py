@@ -432,3 +432,26 @@ def test_ttm_pair_rejects_unsupported():
     with pytest.raises(tk.TuckerError) as e:  # B % 4 != 0 and too few tiles
         tk.ttm_pair(X, 1, 4, 8, 4, 6, F, 2, F, 2, o, o)
     assert e.value.code == tk.TK_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("A,Lp,Lq,Kp,Kq", [(4096, 24, 16, 4, 4), (5000, 12, 20, 7, 3),
+                                          (4099, 8, 2, 8, 1), (9000, 1, 4, 1, 4)])
+def test_ttm_pair_trailing_modes(A, Lp, Lq, Kp, Kq):
+    """The pair kernel for the two trailing modes (slabs of Lp x Lq staged in
+    LDS, the six-mode tensor's root pair): both outputs element-wise against
+    the oracle, including a ragged last block of slabs."""
+    torch, dev = torch_dev()
+    print(f"ttm pair (trailing) A={A} Lp={Lp} Lq={Lq} Kp={Kp} Kq={Kq}", flush=True)
+    g = np.random.default_rng(A + Lp * Lq + Kp + Kq)
+    X = g.standard_normal((A, Lp, Lq)).astype(np.float32)
+    Fp = g.standard_normal((Lp, Kp)).astype(np.float32)
+    Fq = g.standard_normal((Lq, Kq)).astype(np.float32)
+    op = torch.full((A, Kp, Lq), float("nan"), dtype=torch.float32, device=dev)
+    oq = torch.full((A, Lp, Kq), float("nan"), dtype=torch.float32, device=dev)
+    tk.ttm_pair(to_dev(X), A, Lp, 1, Lq, 1, to_dev(Fp), Kp, to_dev(Fq), Kq, op, oq)
+    torch.cuda.synchronize()
+    X64, Fp64, Fq64 = X.astype(np.float64), Fp.astype(np.float64), Fq.astype(np.float64)
+    assert_elementwise(op.cpu().numpy(), O.ttm(X64, Fp64.T, 1), abs_ttm(X64, Fp64.T, 1),
+                       ttm_tol(Lp, "fp32"), "pair tail: mode p")
+    assert_elementwise(oq.cpu().numpy(), O.ttm(X64, Fq64.T, 2), abs_ttm(X64, Fq64.T, 2),
+                       ttm_tol(Lq, "fp32"), "pair tail: mode q")
