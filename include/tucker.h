@@ -394,6 +394,21 @@ int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp
 int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
             void* stream);
 
+/* tk_gram without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments and layouts as tk_gram; the
+ * column-chunk partial sums live in a static device array of 4 Mi doubles
+ * (32 MiB, held by every GPU the library runs on until the process ends),
+ * so the column chunks grow when the partials would not fit (the sums then
+ * run in another fixed order: equal to tk_gram within FP64 rounding, still
+ * deterministic).  Enqueued on `stream`, no synchronisation.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Errors: those of
+ * tk_gram, TK_EUNSUPPORTED when one chunk's partials exceed the array
+ * (more than 1024 rows), TK_EDEVICE if the array's address cannot be taken. */
+int tk_gram_noalloc(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
+                    void* stream);
+
 /* Leading K eigenpairs of `count` symmetric L x L FP64 matrices (device,
  * contiguous), eigenvalues descending, each eigenvector's largest-magnitude
  * entry (lowest index on ties) made positive (Sec. 2.2: the new factor is the

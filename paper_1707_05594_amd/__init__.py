@@ -89,6 +89,7 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "tk_ttm_pair": ([ctypes.c_int, ctypes.c_int, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i64,
                      _vp, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "tk_gram_noalloc": ([ctypes.c_int, _vp, _i64, _i64, _i64, _vp, _vp], ctypes.c_int),
     "tk_eig_leading": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp],
                        ctypes.c_int),
     "tk_eig_full": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp],
@@ -442,6 +443,12 @@ def gram(Y, A, L, B, S, stream=None):
     """S (L x L FP64, device) = Gram of the mode unfolding of Y viewed as [A, L, B]."""
     _check(lib().tk_gram(_dtype_code(Y), _dev_ptr(Y), int(A), int(L), int(B), _dev_ptr(S),
                          _stream_ptr(stream)))
+
+
+def gram_noalloc(Y, A, L, B, S, stream=None):
+    """As gram(), with no device allocation (static scratch area; asynchronous)."""
+    _check(lib().tk_gram_noalloc(_dtype_code(Y), _dev_ptr(Y), int(A), int(L), int(B),
+                                 _dev_ptr(S), _stream_ptr(stream)))
 
 
 def eig_leading(S, K, V0=None, F=None, evals=None, stream=None):

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "device.h"
 #include "internal.h"
@@ -384,3 +385,88 @@ hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_
 }
 
 }  // namespace tk
+
+// ---------------------------------------------------------------------------
+// Allocation-free Gram: the chunk partials live in a file-scope device array
+// instead of memory allocated per call.  The array's name is a host-side
+// stand-in in host code; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address is
+// passed to the kernels.
+// ---------------------------------------------------------------------------
+namespace tk {
+namespace {
+
+constexpr size_t kGramScratchDoubles = (size_t)4 << 20;  // 32 MiB per device
+__device__ __align__(256) double scratch[kGramScratchDoubles];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use).
+int scratch_ptr(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices)
+    return fail(TK_EDEVICE, "no current device for the Gram scratch area");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TK_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TK_OK;
+}
+
+}  // namespace
+}  // namespace tk
+
+extern "C" int tk_gram_noalloc(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B,
+                               double* S, void* stream) {
+  using namespace tk;
+  clear_error();
+  if (!Y || !S) return fail(TK_EINVAL, "null pointer");
+  if (A < 1 || L < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
+  if (L > 1024) return fail(TK_EUNSUPPORTED, "L > 1024");
+  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  const int64_t C = A * B;
+  GramGeom g = gram_geom(L, C);
+  const size_t per_chunk = (size_t)g.npairs * kGT * kGT;
+  if (per_chunk > kGramScratchDoubles)
+    return fail(TK_EUNSUPPORTED,
+                "L=%lld needs %zu doubles of partials per column chunk; the allocation-free "
+                "Gram holds %zu",
+                (long long)L, per_chunk, kGramScratchDoubles);
+  // fewer, longer column chunks when the partials would not fit
+  const int64_t max_chunks = (int64_t)(kGramScratchDoubles / per_chunk);
+  if (g.nchunks > max_chunks) {
+    int64_t cc = (C + max_chunks - 1) / max_chunks;
+    cc = (cc + kGC - 1) / kGC * kGC;
+    g.cchunk = cc;
+    g.nchunks = (C + cc - 1) / cc;
+  }
+  double* part = nullptr;
+  if (int rc = scratch_ptr(&part)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  dim3 grid((unsigned)g.nchunks, (unsigned)g.npairs);
+  if (in_dtype == TK_F64)
+    hipLaunchKernelGGL(gram_partial<double>, grid, dim3(256), 0, st, (const double*)Y, (int)L, B,
+                       C, g.cchunk, g.T, g.npairs, part);
+  else if (in_dtype == TK_F32)
+    hipLaunchKernelGGL(gram_partial<float>, grid, dim3(256), 0, st, (const float*)Y, (int)L, B, C,
+                       g.cchunk, g.T, g.npairs, part);
+  else
+    hipLaunchKernelGGL(gram_partial<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)Y,
+                       (int)L, B, C, g.cchunk, g.T, g.npairs, part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    const int64_t n = L * L;
+    hipLaunchKernelGGL(gram_reduce, dim3((unsigned)((n + kRE - 1) / kRE)), dim3(256), 0, st, part,
+                       (int)L, g.T, g.npairs, (int)g.nchunks, S);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return fail(TK_EDEVICE, "gram: %s", hipGetErrorString(e));
+  return TK_OK;
+}
