@@ -368,7 +368,7 @@ def six_mode_leg(steps, warmup):
     del ctx
     # cost model: node and root-pair timings of random shapes, trained on the GPU
     t2 = time.perf_counter()
-    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=40, seed=1)
+    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=48, seed=1)
     model, losses = cm.train(X, y, steps=3000, lr=3e-3)
     plan = tk.ttm_tree_plan(L, K, "dp", topk=8)
     chosen, pred = plan.learned(model, "f32", "fp32", margin=0.02)

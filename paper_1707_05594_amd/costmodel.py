@@ -76,7 +76,7 @@ def candidate_pairs(L, K, topk=8, trailing=True):
     return list(seen)
 
 
-def random_pair_views(count, seed, min_elems=int(2e7), max_elems=int(1.6e9)):
+def random_pair_views(count, seed, min_elems=int(2e7), max_elems=int(3e9)):
     """Seeded root-pair views (A, Lp, 1, Lq, 1, Kp, Kq) of two trailing modes
     in the slab pair kernel's domain (Lp, Lq multiples of 4 with Lp Lq <= 2048,
     ranks up to 8), with |T| log-uniform in [min_elems, max_elems]: the
@@ -104,7 +104,7 @@ def pair_node_views(pairs, tdtype="f32"):
     return out
 
 
-def measure_pairs(pairs, reps=3, device="cuda:0"):
+def measure_pairs(pairs, reps=10, device="cuda:0"):
     """Time the fused root pair for every view a pair kernel takes (FP32);
     returns features X, log-ms y and rows (view, ms)."""
     import torch
@@ -150,7 +150,7 @@ def random_shapes(count, seed, max_elems=int(1.6e9)):
     return shapes
 
 
-def measure(views, compute="fp32", reps=3, tiles=range(TK_TILE_COUNT), device="cuda:0"):
+def measure(views, compute="fp32", reps=5, tiles=range(TK_TILE_COUNT), device="cuda:0"):
     """Time every (view, tile); returns features X (n x TK_FEATURES), log-ms y."""
     import torch
     dev = torch.device(device)
@@ -175,7 +175,7 @@ def measure(views, compute="fp32", reps=3, tiles=range(TK_TILE_COUNT), device="c
     return np.array(X, dtype=np.float32), np.array(y, dtype=np.float32), rows
 
 
-def training_set(n_shapes=10, n_pairs=40, seed=1, topk=8):
+def training_set(n_shapes=10, n_pairs=48, seed=1, topk=8):
     """Timed training rows: the nodes of the `topk` best trees of `n_shapes`
     random tensors, their root pairs a pair kernel takes, and `n_pairs` random
     trailing-pair views with their two separate root TTMs.  Returns

@@ -552,9 +552,11 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     j.work_off = work;
     work += (int64_t)eig_work_elems(j.L, b->pmax);  // the launch's widest block
   }
+  // warm solves start from the previous factors with K + 4 columns at any L
+  // (a full Jacobi solve of a 64 x 64 Gram costs its CU over a millisecond);
+  // one that does not converge there is redone by the gap-free solver
   jw = jc;
-  for (auto& j : jw)
-    if (j.p != j.L) j.p = std::max(j.K, std::min(j.p, j.K + 4));
+  for (auto& j : jw) j.p = std::max(j.K, std::min(j.p, j.K + 4));
   for (auto& j : jc) j.V0_off = -1;
   {
     // order both tables by the warm block width (stable: ties keep tensor order)
@@ -591,13 +593,13 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     classes(jc, jw, &b->cold_classes);
   }
   b->jobs_h = jc;
-  // subspace jobs (p < L) may fall back to the gap-free solver; job q of the
-  // (sorted) tables owns status word q
+  // subspace jobs (warm p < L) may fall back to the gap-free solver; job q
+  // of the (sorted) tables owns status word q
   std::vector<EigFullJob> fj;
   int64_t fwork = 0;
   for (int q = 0; q < b->n_jobs; ++q) {
     const EigJob& j = jc[q];
-    if (j.p == j.L) continue;
+    if (jw[q].p == j.L) continue;
     EigFullJob f;
     f.L = j.L;
     f.K = j.K;

@@ -75,7 +75,7 @@ def test_learned_selection_on_six_mode_tensor():
     L, K = (64, 48, 40, 32, 24, 16), (8, 8, 6, 6, 4, 4)
     # training data: node shapes of the 8 best trees of random tensors (not this
     # one), the root pairs a pair kernel takes, and random trailing-pair views
-    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=40, seed=1)
+    X, y, rows, prow = cm.training_set(n_shapes=10, n_pairs=48, seed=1)
     print(f"timed {len(rows)} node rows and {len(prow)} fused root pairs", flush=True)
     assert len(prow) >= 8
     model, losses = cm.train(X, y, steps=3000, lr=3e-3)
@@ -87,6 +87,16 @@ def test_learned_selection_on_six_mode_tensor():
     corr = float(np.corrcoef(pred, yc)[0, 1])
     print(f"held-out correlation of log times {corr:.3f}", flush=True)
     assert corr > 0.9
+    # the model's view of the DP tree's root level: separate TTMs or one pass
+    pv = cm.root_pair_view(L, K, tk.ttm_tree_plan(L, K), 0)
+    A, Lp, M, Lq, B, Kp, Kq = pv
+    sep = [tk.ttm_features(A, Lp, M * Lq * B, Kp, "f32", "fp32", t) for t in range(tk.TK_TILE_COUNT)]
+    sep_q = [tk.ttm_features(A * Lp * M, Lq, B, Kq, "f32", "fp32", t)
+             for t in range(tk.TK_TILE_COUNT)]
+    p_sep = (np.exp(model.forward(np.array(sep, np.float32))).min() +
+             np.exp(model.forward(np.array(sep_q, np.float32))).min())
+    p_pair = float(np.exp(model.forward(np.array([tk.pair_features(*pv)], np.float32)))[0])
+    print(f"root level predicted: separate {p_sep:.3f} ms, one pass {p_pair:.3f} ms", flush=True)
     plan = tk.ttm_tree_plan(L, K, "dp", topk=8)
     chosen, pred_ms = plan.learned(model, "f32", "fp32", margin=0.02)
     print(f"chosen rank {chosen} tiles {plan.tiles(chosen)} predicted {pred_ms}", flush=True)
