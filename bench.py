@@ -418,6 +418,58 @@ def six_mode_leg(steps, warmup):
     return res
 
 
+def real_shapes_leg(steps=2):
+    """The paper's real-tensor shapes (Sec. 6.1 table: HCCI, TJLR, SP) filled
+    with uniform random data, FP32, DP tree, HOSVD start: per shape the HOOI
+    invocation time, the tree pass alone and its TTM rate against the FP32
+    MFMA peak (ranks up to 306: the contractions are compute-heavy here), and
+    the rest of the invocation (Grams, gap-free eigensolves, core)."""
+    import torch
+
+    import paper_1707_05594_amd as tk
+    import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, (L, K) in synth.REAL_TENSORS.items():
+        t0 = time.perf_counter()
+        Td = synth.real_tensor_device(name, dev)
+        plan = tk.ttm_tree_plan(L, K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx = tk.hooi_init(Td, K, plan=plan, compute="fp32")
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t1
+        ctx.iterate(1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        errs = ctx.iterate(steps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t2) / steps
+        node = [sorted(x)[1] for x in zip(*[ctx.profile_tree() for _ in range(3)])]
+        nodes = plan.nodes()
+        tree_ms = sum(node)
+        ttm_ms = sum(t for t, nd in zip(node, nodes) if not nd["is_leaf"])
+        flops = 2.0 * plan.cost()
+        tf = flops / (ttm_ms * 1e-3) / 1e12
+        card = 1
+        for x in L:
+            card *= x
+        out[name] = {"L": list(L), "K": list(K), "elements": card, "tree": plan.string(),
+                     "tree_macs": plan.cost(), "hosvd_s": round(t_init, 3),
+                     "value": round(1.0 / dt, 4), "unit": "HOOI iters/s",
+                     "ms_per_step": round(1e3 * dt, 2), "tree_ms_per_pass": round(tree_ms, 2),
+                     "ttm_ms_per_pass": round(ttm_ms, 2), "ttm_tflops": round(tf, 2),
+                     "ttm_frac_fp32_mfma_peak": round(tf / FP32_MFMA_PEAK_TFLOPS, 4),
+                     "rest_ms_per_step": round(1e3 * dt - tree_ms, 2),
+                     "rel_err": errs[-1]}
+        log(f"{name}: {1e3 * dt:.1f} ms per invocation (tree {tree_ms:.1f} ms, TTMs {ttm_ms:.1f} "
+            f"ms at {tf:.1f} TFLOP/s = {tf / FP32_MFMA_PEAK_TFLOPS:.3f} of FP32 MFMA peak), "
+            f"HOSVD {t_init:.2f} s, total leg {time.perf_counter() - t0:.1f} s")
+        del ctx, Td
+        torch.cuda.empty_cache()
+    return out
+
+
 def sthosvd_leg(Td, K, plan, steps):
     """HOSVD against STHOSVD starts on the benchmark tensor: start time, the
     FP64 explicit residual of each start and after `steps` invocations."""
@@ -452,6 +504,7 @@ def main():
     ap.add_argument("--skip-five-mode", action="store_true")
     ap.add_argument("--skip-sthosvd", action="store_true")
     ap.add_argument("--skip-six-mode", action="store_true")
+    ap.add_argument("--skip-real-shapes", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="finish with three device-to-device copies of BYTES bytes "
                          "(dispatches of known size that calibrate the HBM counters)")
@@ -561,6 +614,8 @@ def main():
 
     if not args.skip_six_mode:
         out["six_mode_64x48x40x32x24x16"] = six_mode_leg(args.steps, args.warmup)
+    if not args.skip_real_shapes:
+        out["real_shapes"] = real_shapes_leg()
 
     if not args.skip_batch:
         out["batch"] = batch_leg(args.steps, args.warmup)

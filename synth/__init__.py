@@ -56,6 +56,27 @@ WORKLOADS = {
 }
 
 
+# Real-tensor metadata (Sec. 6.1, table of real tensors): dimension lengths
+# and core lengths.  The paper fills these tensors with random data.
+REAL_TENSORS = {
+    "HCCI": ((672, 672, 627, 16), (279, 279, 153, 14)),
+    "TJLR": ((460, 700, 360, 16, 4), (306, 232, 239, 16, 4)),
+    "SP": ((500, 500, 500, 11, 10), (81, 129, 127, 7, 6)),
+}
+
+
+def real_tensor_device(name: str, device, cfg: int = 7):
+    """The real-tensor shape `name` filled with uniform [0, 1) FP32 values on
+    a torch device, drawn by torch's generator for that device seeded from
+    (SEED_ROOT, cfg, the shape's index).  4.5e9 to 1.4e10 elements: drawn
+    where it is used; parity checks read slices back from the device."""
+    import torch
+    L, _ = REAL_TENSORS[name]
+    g = torch.Generator(device=device)
+    g.manual_seed(SEED_ROOT * 1000 + cfg * 10 + list(REAL_TENSORS).index(name))
+    return torch.rand(L, generator=g, device=device, dtype=torch.float32)
+
+
 def generator(cfg: int, idx: int = 0, stream: int = 0) -> np.random.Generator:
     """Seeded Philox generator for workload `cfg`, tensor `idx`, sub-stream `stream`."""
     return np.random.Generator(np.random.Philox(
