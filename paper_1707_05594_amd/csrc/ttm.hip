@@ -318,6 +318,129 @@ __global__ __launch_bounds__(256) void ttm_wide_scalar_f32(const TIn* __restrict
   wide_scalar_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
+// ------------------------------------------------------------- large ranks --
+// Wide grids whose rank needs more than one LDS-resident factor slice (the
+// real tensors' K_n of 80-306): the slice of 4 KG factor columns is staged
+// kLkRows rows at a time (a block barrier per chunk of rows), so KG is not
+// capped by L; and the K-chunks of one 1024-column tile run as consecutive
+// work items of one XCD (blocks are mapped chunk-fastest within each XCD's
+// share of the grid), so the tile's input comes from HBM once and from that
+// XCD's L2 for the other K-chunks, which read the same rows at about the same
+// time.  SCALAR: lane i of wave w owns flattened columns 256 w + i + 64 j
+// (4-byte loads, any B); else lane i owns columns 256 w + 4 i .. + 3 (16-byte
+// loads, B % 4 == 0, aligned).  Normal loads: the K-chunks re-read the input.
+constexpr int kLkRows = 64;
+
+template <int KG>
+__device__ __forceinline__ void stage_factor_rows(float* FT, const float* __restrict__ F, int l0,
+                                                  int l1, int Kt, int k0) {
+  // FT[(r * kLkRows + (l - l0)) * KG + g] = F[l, k0 + 4 g + r] (0 past K or l1)
+  constexpr int total = 4 * kLkRows * KG;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int g = e % KG;
+    const int t = e / KG;
+    const int l = l0 + t % kLkRows;
+    const int r = t / kLkRows;
+    const int k = k0 + 4 * g + r;
+    FT[e] = (k < Kt && l < l1) ? F[(int64_t)l * Kt + k] : 0.f;
+  }
+}
+
+template <int KG, typename TIn, bool SCALAR>
+__global__ __launch_bounds__(256) void ttm_lk_f32(const TIn* __restrict__ in,
+                                                  const float* __restrict__ F,
+                                                  float* __restrict__ out, int64_t C, int L,
+                                                  int64_t B, int Kt, int chunks, int64_t nwork,
+                                                  int64_t per_xcd) {
+  extern __shared__ float smem[];
+  const int64_t w = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (w >= nwork) return;  // the whole block: no barrier is skipped by part of it
+  const int64_t blk = w / chunks;
+  const int k0 = (int)(w - blk * chunks) * 4 * KG;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c0 = (blk * 4 + wave) * 256;
+  const bool live = c0 < C;  // idle waves still take part in the staging barriers
+  const TIn* p[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t c = SCALAR ? c0 + lane + 64 * j : c0 + 4 * lane + j;
+    // columns past the end read column 0 (always in bounds) and store nothing
+    const int64_t a = c < C ? c / B : 0;
+    const int64_t b = c < C ? c - a * B : 0;
+    p[j] = in + (a * L) * B + b;
+  }
+  f4 acc[KG][4];
+#pragma unroll
+  for (int g = 0; g < KG; ++g)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[g][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int l0 = 0; l0 < L; l0 += kLkRows) {
+    const int l1 = min(L, l0 + kLkRows);
+    __syncthreads();  // every wave is done with the previous rows' factor
+    stage_factor_rows<KG>(smem, F, l0, l1, Kt, k0);
+    __syncthreads();
+    if (!live) continue;
+    const float* ft = smem + (lane & 3) * kLkRows * KG - l0 * KG;
+    if constexpr (SCALAR) {
+      constexpr int U = 8;
+      int l = l0;
+      for (; l + U <= l1; l += U) {
+        float x[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) x[u][j] = Elem<TIn>::to_f32(p[j][(int64_t)(l + u) * B]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int g = 0; g < KG; ++g) {
+            const float fa = ft[(l + u) * KG + g];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+          }
+      }
+      for (; l < l1; ++l) {
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Elem<TIn>::to_f32(p[j][(int64_t)l * B]);
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          const float fa = ft[l * KG + g];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[j], acc[g][j]);
+        }
+      }
+    } else {
+      wide_chain<KG, TIn, false>(p[0], B, ft, l0, l1, acc);
+    }
+  }
+  if (!live) return;
+  if constexpr (SCALAR) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = c0 + lane + 64 * j;
+      if (c >= C) continue;
+      const int64_t a = c / B;
+      float* q = out + (a * Kt) * B + (c - a * B);
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int k = k0 + 4 * g + m;
+          if (k < Kt) q[(int64_t)k * B] = acc[g][j][m];
+        }
+    }
+  } else {
+    const int64_t c = c0 + 4 * lane;
+    if (c < C) {
+      const int64_t a = c / B;
+      wide_store<KG>(out, a, c - a * B, B, Kt, k0, acc);
+    }
+  }
+}
+
 // Slab-aligned variant for runs of B (<= 256) that are not whole 128-byte
 // lines while every slab In[a, :, :] starts on a line: a wave takes
 // 64 / (B / 4) whole slabs, B / 4 lanes each (the rest idle), so no cache
@@ -1225,6 +1348,34 @@ int split_kg(int kg) {
   return pick;
 }
 
+template <typename TIn, int KG, bool SCALAR>
+hipError_t launch_lk_kg(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
+                        float* out, hipStream_t st) {
+  const int64_t C = A * B;
+  const int chunks = (K + 4 * KG - 1) / (4 * KG);
+  const int64_t nwork = ((C + 1023) / 1024) * chunks;
+  const int64_t per_xcd = (nwork + 7) / 8;
+  if (8 * per_xcd > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((ttm_lk_f32<KG, TIn, SCALAR>), dim3((unsigned)(8 * per_xcd)), dim3(256),
+                     (size_t)16 * kLkRows * KG, st, in, F, out, C, L, B, K, chunks, nwork,
+                     per_xcd);
+  return hipGetLastError();
+}
+
+// Large-rank launch: the 16-byte body takes chunks of up to 12 K-groups (48
+// factor columns, accumulators in 248 VGPRs, two waves per SIMD), 8 groups
+// when that gives the same number of chunks; the 4-byte body keeps four
+// pointers and takes 8 groups (at 12 it would hold one wave per SIMD).
+template <typename TIn>
+hipError_t launch_lk(bool wide, const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
+                     float* out, hipStream_t st) {
+  const int need = (K + 3) / 4;
+  if (!wide) return launch_lk_kg<TIn, 8, true>(in, A, L, B, F, K, out, st);
+  const int chunks = (need + 11) / 12;
+  if (8 * chunks >= need) return launch_lk_kg<TIn, 8, false>(in, A, L, B, F, K, out, st);
+  return launch_lk_kg<TIn, 12, false>(in, A, L, B, F, K, out, st);
+}
+
 template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                       float* out, bool stream_in, int tile, hipStream_t st) {
@@ -1247,6 +1398,11 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
     kg_cap = std::max(1, std::min(kSplitLMaxKG, kLdsBudget / (16 * L)));
   }
   int kg = pick_kg(K, kg_cap, grid_blocks(path, A, B));
+  // ranks of 32 and more that would need several K-chunks of the capped
+  // instance: the large-rank kernel (any B except rows, which keep theirs)
+  if (tile == TK_TILE_AUTO && K >= 32 && (K + 3) / 4 > kg &&
+      (path == Path::kWide || path == Path::kWideScalar || path == Path::kTile))
+    return launch_lk<TIn>(path == Path::kWide, in, A, L, B, F, K, out, st);
   if (tile == TK_TILE_SPLITK) kg = split_kg(kg);
   if (stream_in)
     return launch_f32_nt<TIn, true>(path, kg, in, A, L, B, F, K, out, st);

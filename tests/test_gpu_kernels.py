@@ -52,8 +52,19 @@ TTM_CASES = [
     (300, 30, 1001, 20), # 4-byte-load wide path on a full grid, ragged last wave
 ]
 
+# Large ranks (several K-chunks of the capped instance): the factor staged 64
+# rows at a time, K-chunks of a tile as consecutive work items of one XCD.
+LK_CASES = [
+    (3, 700, 100, 232),   # 16-byte body, 12 groups x 5 chunks, last row chunk of 60
+    (2, 672, 627, 153),   # 4-byte body (odd B), 8 groups x 5 chunks, ragged last tile
+    (1000, 161, 14, 81),  # short runs (B < 32) through the 4-byte body, 3 chunks
+    (50, 500, 64, 127),   # 16-byte body, 12 groups x 3 chunks (K = 127, ragged groups)
+    (1, 460, 5345, 306),  # 4-byte body, 10 chunks, one a
+    (7, 65, 1024, 96),    # 16-byte body, 2 chunks, a last row chunk of one row
+]
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES)
+
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES + LK_CASES)
 def test_ttm_fp32(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm fp32 A={A} L={L} B={B} K={K}", flush=True)
@@ -69,7 +80,7 @@ def test_ttm_fp32(A, L, B, K):
                        f"ttm fp32 {A}x{L}x{B} K={K}")
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:])
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES)
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
