@@ -54,9 +54,23 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Smallest value of v over the block (every thread gets it).
+__device__ __forceinline__ int block_min(int v, int* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  int r = red[0];
+#pragma unroll
+  for (int w = 1; w < kFullThreads / 64; ++w) r = min(r, red[w]);
+  return r;
+}
+
 struct FullShared {
   double red[kFullThreads / 64];
   double scal[4];
+  int redi[kFullThreads / 64];
   int flag, lo;
 };
 
@@ -144,11 +158,20 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     const double half = 0.5 * t * block_sum(pv, sh.red);
     for (int k = tid; k < m; k += kFullThreads) w[k] = w[k] - half * v[k];
     __syncthreads();
-    // A' -= v w^T + w v^T
-    for (int k = 0; k < m; ++k) {
-      const double vk = v[k], wk = w[k];
-      double* Ar = Ap + (int64_t)k * L;
-      for (int i = tid; i < m; i += kFullThreads) Ar[i] = Ar[i] - vk * w[i] - wk * v[i];
+    // A' -= v w^T + w v^T, thread by column: eight rows of its column are
+    // loaded together (a row-by-row loop waited one memory latency per row)
+    for (int i = tid; i < m; i += kFullThreads) {
+      const double wi = w[i], vi = v[i];
+      double* col = Ap + i;
+      int k = 0;
+      for (; k + 8 <= m; k += 8) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[(int64_t)(k + u) * L];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) col[(int64_t)(k + u) * L] = a[u] - v[k + u] * wi - w[k + u] * vi;
+      }
+      for (; k < m; ++k) col[(int64_t)k * L] = col[(int64_t)k * L] - v[k] * wi - w[k] * vi;
     }
     __syncthreads();
   }
@@ -172,66 +195,93 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     Zt[i] = (i / L == i % L) ? 1.0 : 0.0;
   __syncthreads();
 
-  // ---- 2. implicit QL with Wilkinson shifts; Z accumulates the rotations
+  // ---- 2. implicit QL with Wilkinson shifts; Z accumulates the rotations.
+  // The tridiagonal matrix moves to LDS (the reflector buffers v and w are
+  // free now): one thread chases the bulge through it, so its every access is
+  // on that thread's critical path.
+  double* dl = lds;
+  double* el = lds + L;
+  for (int i = tid; i < L; i += kFullThreads) {
+    dl[i] = d[i];
+    el[i] = e[i];
+  }
+  __syncthreads();
   const double thresh = 2.220446049250313e-16 * sh.scal[3];
   for (int l = 0; l < L; ++l) {
     for (int sweep = 0;; ++sweep) {
+      // m: the first index >= l whose off-diagonal entry is negligible (L - 1
+      // if none), searched by the whole block
+      int mloc = L - 1;
+      for (int i = l + tid; i < L - 1; i += kFullThreads)
+        if (fabs(el[i]) <= thresh) {
+          mloc = i;
+          break;
+        }
+      const int m = block_min(mloc, sh.redi);
+      if (m == l) break;  // converged (uniform over the block)
       if (tid == 0) {
-        int m = l;
-        while (m < L - 1 && fabs(e[m]) > thresh) ++m;
-        int lo = m;  // lowest rotated index; m == l: converged
-        if (m != l) {
-          if (sweep >= kQlMaxSweeps) {
-            sh.flag = 1;
-          } else {
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-            double r = hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + copysign(r, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool split = false;
-            for (int i = m - 1; i >= l; --i) {
-              const double f = s * e[i];
-              const double b = c * e[i];
-              r = hypot(f, g);
-              e[i + 1] = r;
-              if (r == 0.0) {  // underflow: the matrix splits here, restart
-                d[i + 1] -= p;
-                e[m] = 0.0;
-                split = true;
-                break;
-              }
-              s = f / r;
-              c = g / r;
-              g = d[i + 1] - p;
-              r = (d[i] - g) * s + 2.0 * c * b;
-              p = s * r;
-              d[i + 1] = g + p;
-              g = c * r - b;
-              cs[i] = c;
-              sn[i] = s;
-              lo = i;
+        int lo = m;  // lowest rotated index
+        if (sweep >= kQlMaxSweeps) {
+          sh.flag = 1;
+        } else {
+          double g = (dl[l + 1] - dl[l]) / (2.0 * el[l]);
+          double r = hypot(g, 1.0);
+          g = dl[m] - dl[l] + el[l] / (g + copysign(r, g));
+          double s = 1.0, c = 1.0, p = 0.0;
+          bool split = false;
+          for (int i = m - 1; i >= l; --i) {
+            const double f = s * el[i];
+            const double b = c * el[i];
+            r = hypot(f, g);
+            el[i + 1] = r;
+            if (r == 0.0) {  // underflow: the matrix splits here, restart
+              dl[i + 1] -= p;
+              el[m] = 0.0;
+              split = true;
+              break;
             }
-            if (!split) {
-              d[l] -= p;
-              e[l] = g;
-              e[m] = 0.0;
-            }
+            s = f / r;
+            c = g / r;
+            g = dl[i + 1] - p;
+            r = (dl[i] - g) * s + 2.0 * c * b;
+            p = s * r;
+            dl[i + 1] = g + p;
+            g = c * r - b;
+            cs[i] = c;
+            sn[i] = s;
+            lo = i;
+          }
+          if (!split) {
+            dl[l] -= p;
+            el[l] = g;
+            el[m] = 0.0;
           }
         }
         sh.lo = lo;
-        sh.scal[2] = (double)m;
       }
       __syncthreads();
-      const int m = (int)sh.scal[2];
-      const int lo = sh.lo;
       if (sh.flag) break;
-      if (m == l) break;
+      const int lo = sh.lo;
       // columns lo .. m of Z: rotation i mixes columns i and i+1, applied for
-      // i = m-1 down to lo; each thread carries column i+1 of its rows
+      // i = m-1 down to lo; each thread carries column i+1 of its rows.  Rows
+      // of Zt are read eight rotations ahead (independent loads in flight
+      // together; a batch never reads a row it or a later batch writes).
       if (lo < m) {
         for (int r = tid; r < L; r += kFullThreads) {
           double znext = Zt[(int64_t)m * L + r];
-          for (int i = m - 1; i >= lo; --i) {
+          int i = m - 1;
+          for (; i - 7 >= lo; i -= 8) {
+            double z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) z[u] = Zt[(int64_t)(i - u) * L + r];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const double c = cs[i - u], s = sn[i - u];
+              Zt[(int64_t)(i - u + 1) * L + r] = s * z[u] + c * znext;
+              znext = c * z[u] - s * znext;
+            }
+          }
+          for (; i >= lo; --i) {
             const double zi = Zt[(int64_t)i * L + r];
             const double c = cs[i], s = sn[i];
             Zt[(int64_t)(i + 1) * L + r] = s * zi + c * znext;
@@ -244,6 +294,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     }
     if (sh.flag) break;
   }
+  for (int i = tid; i < L; i += kFullThreads) d[i] = dl[i];
   __syncthreads();
 
   // ---- 3. the K largest eigenvalues, descending (lower index first on ties)

@@ -135,7 +135,11 @@ struct tk_ctx {
   // ev_fac[n] once the new factor (FP64 and compute copy) is written; the main
   // stream waits on ev_fac[n] only before it next uses factor n, so a solve
   // overlaps the rest of its own tree pass and the start of the next one.
-  hipStream_t side = nullptr;
+  // Up to kMaxSide side streams, mode n's solve on sides[n % count]: the
+  // solves of different modes (one workgroup each) run side by side.
+  static constexpr int kMaxSide = 4;
+  std::vector<hipStream_t> sides;
+  hipStream_t side_of(int n) const { return sides[(size_t)n % sides.size()]; }
   // Device work runs on `st`.  With CU partitioning (the default) `st` is an
   // internal stream masked away from a few CUs that only the side stream
   // uses, so the latency-bound eigensolver never shares a CU with the
@@ -151,7 +155,7 @@ struct tk_ctx {
   int passes = 0;  // pipelined passes so far (alternates the root-subtree order)
 
   ~tk_ctx() {
-    if (side) (void)hipStreamSynchronize(side);
+    for (hipStream_t q : sides) (void)hipStreamSynchronize(q);
     if (own_main) (void)hipStreamSynchronize(st);
     void* ptrs[] = {ws, F64a, F64b, wdtype == TK_F64 ? nullptr : Fc,
                     wdtype == TK_F64 ? nullptr : Fcb, S, ev, eigwork, status, jobs,
@@ -164,7 +168,7 @@ struct tk_ctx {
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_fac)
       if (e) (void)hipEventDestroy(e);
-    if (side) (void)hipStreamDestroy(side);
+    for (hipStream_t q : sides) (void)hipStreamDestroy(q);
     if (own_main) (void)hipStreamDestroy(st);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
@@ -208,11 +212,19 @@ int reserved_side_cus() {
   return n < 0 ? 0 : std::min(n, 64);
 }
 
-// Create the side stream and, when CU partitioning is available, the
+// Create the side streams and, when CU partitioning is available, the
 // internal main stream; on any failure of the masked variant fall back to
-// one unmasked side stream and the caller's stream.
+// unmasked side streams and the caller's stream.  One side stream, unless a
+// mode goes straight to the gap-free solver (K above the subspace limit):
+// those solves take 10-300 ms each, and one stream per mode (at most
+// kMaxSide) runs them side by side (HCCI 892 -> 344 ms per invocation).
+// Small warm solves stay on one stream: with four, the six-mode tensor's
+// invocation went from 4.15 to 5.10 ms.
 hipError_t create_streams(tk_ctx* c) {
   const int reserve = reserved_side_cus();
+  bool heavy = false;
+  for (int n = 0; n < c->s.N; ++n) heavy = heavy || c->full_only[n];
+  const int nside = heavy ? std::max(1, std::min(c->s.N, tk_ctx::kMaxSide)) : 1;
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -221,29 +233,40 @@ hipError_t create_streams(tk_ctx* c) {
     const int words = (ncu + 31) / 32;
     std::vector<uint32_t> side_mask(words, 0u), main_mask(words, 0u);
     for (int i = 0; i < ncu; ++i) (i < reserve ? side_mask : main_mask)[i / 32] |= 1u << (i % 32);
-    hipStream_t side = nullptr, main = nullptr;
-    hipError_t e1 = hipExtStreamCreateWithCUMask(&side, (uint32_t)words, side_mask.data());
+    std::vector<hipStream_t> sides;
+    hipStream_t main = nullptr;
+    hipError_t e1 = hipSuccess;
+    for (int k = 0; k < nside && e1 == hipSuccess; ++k) {
+      hipStream_t q = nullptr;
+      e1 = hipExtStreamCreateWithCUMask(&q, (uint32_t)words, side_mask.data());
+      if (e1 == hipSuccess) sides.push_back(q);
+    }
     hipError_t e2 = e1 == hipSuccess
                         ? hipExtStreamCreateWithCUMask(&main, (uint32_t)words, main_mask.data())
                         : e1;
     hipError_t e3 = e2 == hipSuccess ? hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) : e2;
     hipError_t e4 = e3 == hipSuccess ? hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) : e3;
     if (e4 == hipSuccess) {
-      c->side = side;
+      c->sides = sides;
       c->user = c->st;
       c->st = main;
       c->own_main = true;
       c->side_cus = reserve;
       return hipSuccess;
     }
-    if (side) (void)hipStreamDestroy(side);
+    for (hipStream_t q : sides) (void)hipStreamDestroy(q);
     if (main) (void)hipStreamDestroy(main);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     c->ev_in = c->ev_out = nullptr;
     (void)hipGetLastError();
   }
-  return hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  for (int k = 0; k < nside; ++k) {
+    hipStream_t q = nullptr;
+    if ((e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking)) != hipSuccess) return e;
+    c->sides.push_back(q);
+  }
+  return hipSuccess;
 }
 
 // Every mode's leading eigenpairs on the main stream: subspace iteration
@@ -374,19 +397,20 @@ int tree_pass(tk_ctx* c, int fold_dst, bool keep, hipEvent_t* ev_t, bool update 
         TK_HIP(hipMemcpyAsync(c->leaves[n], in, (size_t)c->leaf_elems[n] * dtype_size(in_dt),
                               hipMemcpyDeviceToDevice, c->st));
       if (update) {
+        hipStream_t side = c->side_of(n);
         TK_HIP(hipEventRecord(c->ev_leaf[n], c->st));
-        TK_HIP(hipStreamWaitEvent(c->side, c->ev_leaf[n], 0));
+        TK_HIP(hipStreamWaitEvent(side, c->ev_leaf[n], 0));
         const EigJob& j = c->jobs_h[n];
         if (!c->full_only[n])
           TK_HIP(launch_eig(1, c->jobs, n, j.L, j.p, c->S, c->F64a, c->F64b, c->ev, c->eigwork,
-                            c->status, c->status + s.N, c->maxit_warm, c->eig_tol, c->side));
+                            c->status, c->status + s.N, c->maxit_warm, c->eig_tol, side));
         TK_HIP(launch_eig_full(1, c->fjobs + n, j.L, j.K, c->S, c->F64b, c->ev, c->fwork,
-                               c->status, c->side));
+                               c->status, side));
         if (c->wdtype != TK_F64)
           TK_HIP(launch_convert(TK_F64, c->wdtype, c->F64b + c->fofs[n],
                                 (char*)c->Fcb + c->fofs[n] * dtype_size(c->wdtype),
-                                (int64_t)(c->fofs[n + 1] - c->fofs[n]), c->side));
-        TK_HIP(hipEventRecord(c->ev_fac[n], c->side));
+                                (int64_t)(c->fofs[n + 1] - c->fofs[n]), side));
+        TK_HIP(hipEventRecord(c->ev_fac[n], side));
       }
       if (fold_dst >= 0 && n == c->fold_leaf) {
         TK_HIP(launch_ttm(in_dt, c->core_compute, in, A, L, B, c->fc(n), s.K[n], c->core, c->st));
