@@ -53,8 +53,10 @@ struct TtmNodeDesc {
   const float* F;  // L x K row-major
   int64_t A, B, nbt;
   int L, K, na, nb;
-  int path;  // kGrouped*: the tile body the node's items run
-  int pad_;
+  int path;   // kGrouped*: the tile body the node's items run
+  int lines;  // 1: every run the body reads is whole 128-byte lines (B, or L for
+              // rows, times the element size), so streaming loads fetch no
+              // line twice; 0: normal loads even for an input read once
 };
 // Kernel body and item count of a node viewed as [A, L, B] (in_bytes: input
 // element size): the wide body (B % 4 == 0, B >= 16, aligned), the LDS row
@@ -74,6 +76,14 @@ int ttm_grouped_row_stage_max_L();
 hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
                               int n_items, int* counter, int Lmax, int grid, bool stream_in,
                               hipStream_t st);
+
+// The same queue for kGroupedRowsScalar nodes only, with the barrier-free
+// single-element row body (a kernel of its own: its registers would lower the
+// occupancy of the other bodies).  LDS: ttm_grouped_rows_lds(Lmax).
+size_t ttm_grouped_rows_lds(int Lmax);
+hipError_t launch_ttm_grouped_rows(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
+                                   int n_items, int* counter, int Lmax, int grid, bool stream_in,
+                                   hipStream_t st);
 
 // Gram S = Y_(n) Y_(n)^T (gram.hip); `part` holds gram_workspace_elems(L, A*B) doubles
 hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,

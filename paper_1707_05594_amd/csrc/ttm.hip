@@ -1094,20 +1094,61 @@ __global__ __launch_bounds__(256, 3) void ttm_grouped(const TtmNodeDesc* __restr
     if (it >= n_items) break;
     const int2 w = items[it];
     const TtmNodeDesc d = nodes[w.x];
-    if (d.path == kGroupedWide)
-      wide_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0, smem);
-    else if (d.path == kGroupedWideScalar)
-      wide_scalar_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0,
-                                   smem);
-    else if (d.path == kGroupedRows)
-      rows_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
-    else if (d.path == kGroupedRowsScalar)
-      rows_lds_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
-    else if (d.path == kGroupedRowsDirect)
-      rows_direct_body<4, TIn, NT>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
-    else
+    // streaming loads only where no 128-byte line is shared between runs
+    const bool nt = NT && d.lines;
+    if (d.path == kGroupedWide) {
+      if (nt)
+        wide_body<4, TIn, true>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0,
+                                smem);
+      else
+        wide_body<4, TIn, false>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K, w.y, 0,
+                                 smem);
+    } else if (d.path == kGroupedWideScalar) {
+      if (nt)
+        wide_scalar_body<4, TIn, true>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K,
+                                       w.y, 0, smem);
+      else
+        wide_scalar_body<4, TIn, false>((const TIn*)d.in, d.F, d.out, d.A * d.B, d.L, d.B, d.K,
+                                        w.y, 0, smem);
+    } else if (d.path == kGroupedRows) {
+      if (nt)
+        rows_body<4, TIn, true>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+      else
+        rows_body<4, TIn, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    } else if (d.path == kGroupedRowsScalar) {
+      rows_lds_body<4, TIn, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    } else if (d.path == kGroupedRowsDirect) {
+      if (nt)
+        rows_direct_body<4, TIn, true>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+      else
+        rows_direct_body<4, TIn, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0,
+                                        smem);
+    } else
       tile_body<4, TIn>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.B, d.K, d.na, d.nb, d.nbt, w.y,
                         0, smem);
+  }
+}
+
+// Persistent grouped launch for the B == 1 nodes whose rows cannot be read 16
+// bytes at a time (odd L): the barrier-free single-element row body (each
+// wave its own LDS tile, the next chunk prefetched into registers), in a
+// kernel of its own so that the registers it needs do not set the occupancy
+// of the grouped kernel's other bodies.
+template <typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_grouped_rows(const TtmNodeDesc* __restrict__ nodes,
+                                                        const int2* __restrict__ items,
+                                                        int n_items, int* __restrict__ counter) {
+  extern __shared__ float smem[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();  // every thread has read s_item and finished the previous item
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const TtmNodeDesc d = nodes[w.x];
+    rows_body<4, TIn, NT, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
   }
 }
 
@@ -1561,6 +1602,14 @@ void ttm_grouped_geometry(const void* in, const float* out, int in_bytes, int64_
     d->path = kGroupedTile;
     *tiles = ((A + d->na - 1) / d->na) * d->nbt;
   }
+  const int64_t run = (d->path == kGroupedRows || d->path == kGroupedRowsDirect ||
+                       d->path == kGroupedRowsScalar)
+                          ? L
+                          : B;
+  d->lines = (d->path != kGroupedTile && (run * in_bytes) % 128 == 0 &&
+              (uintptr_t)in % 128 == 0)
+                 ? 1
+                 : 0;
 }
 
 size_t ttm_grouped_lds(int Lmax) {
@@ -1591,6 +1640,28 @@ hipError_t launch_ttm_grouped(int in_dtype, const TtmNodeDesc* nodes, const int2
       TK_GROUPED(uint16_t, false);
   }
 #undef TK_GROUPED
+  return hipGetLastError();
+}
+
+size_t ttm_grouped_rows_lds(int Lmax) { return (size_t)16 * Lmax * 4 + kRowStageBytes; }
+
+hipError_t launch_ttm_grouped_rows(int in_dtype, const TtmNodeDesc* nodes, const int2* items,
+                                   int n_items, int* counter, int Lmax, int grid, bool stream_in,
+                                   hipStream_t st) {
+  if (n_items == 0) return hipSuccess;
+  const size_t lds = ttm_grouped_rows_lds(Lmax);
+  if (lds > (size_t)kLdsBudget) return hipErrorInvalidValue;
+  grid = std::max(1, std::min(grid, n_items));
+  // odd-length rows never end on a 128-byte line: consecutive rows share their
+  // boundary lines, so the loads stay normal (cached) even for an input read
+  // once, which non-temporal loads would fetch twice
+  (void)stream_in;
+  if (in_dtype == TK_F32)
+    hipLaunchKernelGGL((ttm_grouped_rows<float, false>), dim3(grid), dim3(256), lds, st, nodes,
+                       items, n_items, counter);
+  else
+    hipLaunchKernelGGL((ttm_grouped_rows<uint16_t, false>), dim3(grid), dim3(256), lds, st,
+                       nodes, items, n_items, counter);
   return hipGetLastError();
 }
 
