@@ -1315,16 +1315,22 @@ hipError_t launch_f32_kg(Path path, const TIn* in, int64_t A, int L, int64_t B, 
                          L, B, K);
     }
   } else if (path == Path::kWideScalar) {
+    // runs of B % 4 != 0 elements are never whole 128-byte lines: consecutive
+    // rows share their boundary lines, so the loads stay normal (cached)
     const int64_t C = A * B;
     dim3 grid((unsigned)((C + 1023) / 1024), (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_wide_scalar_f32<KG, TIn, NT>), grid, dim3(256), (size_t)16 * L * KG,
-                       st, in, F, out, C, L, B, K);
+    hipLaunchKernelGGL((ttm_wide_scalar_f32<KG, TIn, false>), grid, dim3(256),
+                       (size_t)16 * L * KG, st, in, F, out, C, L, B, K);
   } else if (path == Path::kWideSplitL) {
     if (KG > kSplitLMaxKG || splitl_lds(L, KG) > (size_t)kLdsBudget) return hipErrorInvalidValue;
     const int64_t C = A * B;
     dim3 grid((unsigned)((C + 255) / 256), (unsigned)chunks);
-    hipLaunchKernelGGL((ttm_wide_splitl_f32<KG, TIn, NT>), grid, dim3(256), splitl_lds(L, KG), st,
-                       in, F, out, C, L, B, K);
+    if (NT && (B * sizeof(TIn)) % 128 == 0)
+      hipLaunchKernelGGL((ttm_wide_splitl_f32<KG, TIn, true>), grid, dim3(256),
+                         splitl_lds(L, KG), st, in, F, out, C, L, B, K);
+    else
+      hipLaunchKernelGGL((ttm_wide_splitl_f32<KG, TIn, false>), grid, dim3(256),
+                         splitl_lds(L, KG), st, in, F, out, C, L, B, K);
   } else if (path == Path::kRows) {
     dim3 grid((unsigned)((A + 255) / 256), (unsigned)chunks);
     const size_t staged = (size_t)16 * L * KG + kRowStageBytes;
