@@ -199,6 +199,22 @@ __global__ __launch_bounds__(kPairThreads, 2) void ttm_pair_f32(
     }
 }
 
+// q = e / d and *rem = e % d for 0 <= e < 2^22, d >= 1, inv = 1.0f / d: the
+// float quotient is off by at most one and is corrected.
+__device__ __forceinline__ int small_divmod(int e, int d, float inv, int* rem) {
+  int q = (int)((float)e * inv);
+  int r = e - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+  *rem = r;
+  return q;
+}
+
 // ---- the two trailing modes (M = 1, B = 1): slabs T[a] of Lp x Lq elements
 // A block stages NA consecutive slabs (contiguous in T) in LDS with 16-byte
 // loads, then forms both outputs from LDS on the VALU:
@@ -230,17 +246,30 @@ __global__ __launch_bounds__(kPairThreads) void ttm_pair_tail_f32(
   const int64_t a0 = (int64_t)blockIdx.x * NA;
   const int na = (int)min<int64_t>(NA, A - a0);
   const int per = Lp * Lq;
-  const int64_t n = (int64_t)na * per;
+  const int n = na * per;  // at most 6144 + 2048 elements
   const float* src = in + a0 * per;
+  const float inv_per = 1.0f / (float)per, inv_lq = 1.0f / (float)Lq;
   // 16-byte loads of the contiguous chunk (per % 4 == 0: every slab, hence
-  // the chunk, starts on 16 bytes), scattered into the padded rows
-  for (int64_t v = tid; v < n / 4; v += kPairThreads) {
+  // the chunk, starts on 16 bytes), scattered into the padded rows.  The
+  // slab, row and column of an element come from one small-integer division
+  // pair per four elements (float reciprocals, corrected to exact)
+  for (int v = tid; v < n / 4; v += kPairThreads) {
     const f4 x = *reinterpret_cast<const f4*>(src + 4 * v);
+    int r;
+    const int as = small_divmod(4 * v, per, inv_per, &r);
+    int col;
+    int row = small_divmod(r, Lq, inv_lq, &col);
+    float* srow = S + as * slab;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int e = (int)(4 * v + c);
-      const int as = e / per, r = e % per;
-      S[as * slab + (r / Lq) * pitch + r % Lq] = x[c];
+      srow[row * pitch + col] = x[c];
+      if (++col == Lq) {  // a slab ends on a row end (per = Lp * Lq)
+        col = 0;
+        if (++row == Lp) {
+          row = 0;
+          srow += slab;
+        }
+      }
     }
   }
   __syncthreads();
