@@ -8,21 +8,32 @@
 //   1. Householder tridiagonalisation  Q^T S Q = tridiag(d, e),
 //      Q = H_0 H_1 ... H_{L-3},  H_j = I - tau_j v_j v_j^T acting on rows
 //      j+1 .. L-1 (v_j stored in row j of the work copy of S, v_j[j+1] = 1).
-//   2. Implicit QL iteration with Wilkinson shifts on (d, e), accumulating
-//      the plane rotations into Z (eigenvectors of the tridiagonal matrix);
-//      one thread chases the bulge and records the rotations, then every
-//      thread applies them to its rows of Z.
-//   3. Ranks of the eigenvalues (descending, lower index first on ties): the
-//      K largest and their columns of Z.
+//   2. L < kInvItMinL: implicit QL iteration with Wilkinson shifts on (d, e),
+//      accumulating the plane rotations into Z (eigenvectors of the
+//      tridiagonal matrix); one thread chases the bulge and records the
+//      rotations, then every thread applies them to its rows of Z; then the
+//      ranks of the eigenvalues (descending, lower index first on ties) pick
+//      the K largest and their columns of Z.
+//   2'. L >= kInvItMinL (as the paper's expert driver does): the K largest
+//      eigenvalues by bisection on Sturm counts, one thread per eigenvalue,
+//      then their vectors by inverse iteration with the LU factors of
+//      T - lambda I (partial pivoting), one thread per vector, then two
+//      passes of modified Gram-Schmidt over the K vectors by the whole block
+//      (inverse iteration leaves residuals of order eps ||T||; close
+//      eigenvalues only cost orthogonality, which the passes restore).  This
+//      avoids the L^3 rotation accumulation, which on one CU took most of a
+//      large solve.
 // A second kernel (a grid of column blocks per matrix) applies Q to the K
 // selected columns (reflectors in reverse order, the block in LDS) and the
 // sign rule (largest-magnitude entry of each vector positive, lowest row on
 // ties).
 //
 // Work area per matrix (eig_full_work_elems): A (L x L), Zt (L x L, Zt[i][r] =
-// Z[r][i], so a rotation of columns i, i+1 of Z reads two rows), d, e, tau,
-// the selection (as doubles), 4 L, and a done flag that the first kernel sets
-// (1: solved in this launch) and the second reads.
+// Z[r][i], so a rotation of columns i, i+1 of Z reads two rows; the inverse-
+// iteration path writes its vectors to rows 0 .. K-1), d, e, tau, the
+// selection (as doubles), 4 L, a done flag that the first kernel sets (1:
+// solved in this launch) and the second reads, and for L >= kInvItMinL the
+// inverse-iteration scratch (6 L doubles per working thread).
 //
 // Status word of a job: 0 solved, 1 not converged, 2 non-finite values.  A
 // job marked only_if_failed runs only when its status word is 1 (the
@@ -66,6 +77,113 @@ __device__ __forceinline__ int block_min(int v, int* red) {
   for (int w = 1; w < kFullThreads / 64; ++w) r = min(r, red[w]);
   return r;
 }
+
+// ---- leading eigenpairs of the tridiagonal matrix by bisection and inverse
+// iteration (the paper's route: the K wanted eigenvalues by Sturm-count
+// bisection, their vectors by inverse iteration, then the back-transform),
+// for L >= kInvItMinL, where accumulating every QL rotation into an L x L
+// matrix on one CU is what the solve spends its time on.
+constexpr int kInvItMinL = 192;
+constexpr int kInvItIters = 3;
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kSafMin = 2.2250738585072014e-308;
+
+// Number of eigenvalues of tridiag(e, d, e) below x (Sturm sequence of the
+// LDL^T factorisation of T - x I; pivots below pivmin in magnitude replaced).
+__device__ int sturm_count(const double* d, const double* e2, int L, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += q < 0.0;
+  for (int i = 1; i < L; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// Eigenvalue j (ascending, 0-based) in [lo, hi] by bisection to full precision.
+__device__ double bisect_eig(const double* d, const double* e2, int L, int j, double lo,
+                             double hi, double pivmin) {
+  for (int it = 0; it < 256; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double tol = 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + pivmin;
+    if (hi - lo <= tol || mid == lo || mid == hi) break;
+    if (sturm_count(d, e2, L, mid, pivmin) <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// LU factorisation with partial pivoting of T - lam I (U with two
+// superdiagonals u0, u1, u2; multipliers m; pv: rows i and i+1 swapped).
+// A zero pivot is replaced by eps ||T||.
+__device__ void tri_lu(const double* d, const double* e, int L, double lam, double tiny,
+                       double* __restrict__ u0, double* __restrict__ u1,
+                       double* __restrict__ u2, double* __restrict__ m,
+                       double* __restrict__ pv) {
+  double a = d[0] - lam;
+  double b = L > 1 ? e[0] : 0.0;
+  for (int i = 0; i + 1 < L; ++i) {
+    const double c = e[i];
+    const double an = d[i + 1] - lam;
+    const double bn = i + 2 < L ? e[i + 1] : 0.0;
+    if (fabs(a) >= fabs(c)) {
+      if (a == 0.0) a = tiny;
+      const double mu = c / a;
+      u0[i] = a;
+      u1[i] = b;
+      u2[i] = 0.0;
+      m[i] = mu;
+      pv[i] = 0.0;
+      a = an - mu * b;
+      b = bn;
+    } else {
+      const double mu = a / c;
+      u0[i] = c;
+      u1[i] = an;
+      u2[i] = bn;
+      m[i] = mu;
+      pv[i] = 1.0;
+      a = b - mu * an;
+      b = -mu * bn;
+    }
+  }
+  u0[L - 1] = a == 0.0 ? tiny : a;
+}
+
+// x = (T - lam I)^-1 y through the factors (y is overwritten).
+__device__ void tri_solve(int L, const double* __restrict__ u0, const double* __restrict__ u1,
+                          const double* __restrict__ u2, const double* __restrict__ m,
+                          const double* __restrict__ pv, double* __restrict__ y,
+                          double* __restrict__ x) {
+  for (int i = 0; i + 1 < L; ++i) {
+    if (pv[i] != 0.0) {
+      const double t = y[i];
+      y[i] = y[i + 1];
+      y[i + 1] = t;
+    }
+    y[i + 1] -= m[i] * y[i];
+  }
+  double x1 = 0.0, x2 = 0.0;  // x[i + 1], x[i + 2]
+  for (int i = L - 1; i >= 0; --i) {
+    const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) / u0[i];
+    x[i] = xi;
+    x2 = x1;
+    x1 = xi;
+  }
+}
+
+// Work area of one matrix: A, Zt, d, e, tau, sel, done; then, for the
+// inverse-iteration path, a scratch slot of 6 L doubles per thread that
+// works (at most one per thread of the block).
+__host__ __device__ inline int64_t eig_full_base_elems(int L) {
+  return 2 * (int64_t)L * L + 4 * (int64_t)L + 1;
+}
+__host__ __device__ inline int invit_slots(int L) { return L < kFullThreads ? L : kFullThreads; }
 
 struct FullShared {
   double red[kFullThreads / 64];
@@ -191,6 +309,103 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     for (int i = 0; i < L; ++i) tst = fmax(tst, fabs(d[i]) + fabs(e[i]));
     sh.scal[3] = tst;
   }
+  __syncthreads();
+  int bad = 0;
+  if (L >= kInvItMinL) {
+    // ---- 2'. bisection for the K largest eigenvalues, inverse iteration for
+    // their vectors (rows 0 .. K-1 of Zt, largest first; sel[c] = c)
+    double* dl = lds;
+    double* el = lds + L;
+    double* e2 = lds + 2 * L;
+    for (int i = tid; i < L; i += kFullThreads) {
+      dl[i] = d[i];
+      el[i] = e[i];
+      e2[i] = e[i] * e[i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double tn = 0.0, lo = 0.0, hi = 0.0, emax = 0.0;
+      for (int i = 0; i < L; ++i) {
+        const double r = fabs(el[i]) + (i ? fabs(el[i - 1]) : 0.0);
+        tn = fmax(tn, fabs(dl[i]) + r);
+        lo = i ? fmin(lo, dl[i] - r) : dl[i] - r;
+        hi = i ? fmax(hi, dl[i] + r) : dl[i] + r;
+        if (i + 1 < L) emax = fmax(emax, e2[i]);
+      }
+      if (!(tn > 0.0)) tn = 1.0;  // the zero matrix: any orthonormal basis
+      sh.scal[0] = lo - 2.0 * kEps * tn - kSafMin;
+      sh.scal[1] = hi + 2.0 * kEps * tn + kSafMin;
+      sh.scal[2] = kSafMin * fmax(1.0, emax);
+      sh.scal[3] = tn;
+    }
+    __syncthreads();
+    const double lo = sh.scal[0], hi = sh.scal[1], pivmin = sh.scal[2], tn = sh.scal[3];
+    for (int t = tid; t < K; t += kFullThreads) {
+      const double lam = bisect_eig(dl, e2, L, L - 1 - t, lo, hi, pivmin);
+      d[t] = lam;  // d now holds the selected eigenvalues, largest first
+      sel[t] = (double)t;
+      bad |= !isfinite(lam);
+    }
+    // inverse iteration, one thread per vector (scratch slots of 6 L doubles);
+    // every vector comes out with a residual of order eps ||T||, and close
+    // eigenvalues only cost orthogonality, which the block restores below
+    const int slots = invit_slots(L);
+    double* scr = work_base + job.work_off + eig_full_base_elems(L) + (int64_t)tid * 6 * L;
+    const double tiny = kEps * tn;
+    for (int t = tid; t < K && tid < slots; t += slots) {
+      double* u0 = scr;
+      double* u1 = u0 + L;
+      double* u2 = u1 + L;
+      double* mm = u2 + L;
+      double* pv = mm + L;
+      double* y = pv + L;
+      double* x = Zt + (int64_t)t * L;
+      tri_lu(dl, el, L, d[t], tiny, u0, u1, u2, mm, pv);
+      // deterministic start vector with entries in [0.5, 1.5)
+      for (int i = 0; i < L; ++i)
+        x[i] = 0.5 + (double)(((uint64_t)i * 2654435761u + (uint64_t)t * 97u) % 1000u) * 1e-3;
+      for (int it = 0; it < kInvItIters; ++it) {
+        double nrm = 0.0;
+        for (int i = 0; i < L; ++i) nrm = fma(x[i], x[i], nrm);
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < L; ++i) y[i] = x[i] * inv;
+        tri_solve(L, u0, u1, u2, mm, pv, y, x);
+      }
+    }
+    __syncthreads();
+    // modified Gram-Schmidt over the K vectors, largest eigenvalue first, twice
+    // (the second pass makes exactly repeated eigenvalues orthonormal to
+    // rounding): step t removes x_t's direction from every later vector, the
+    // four waves taking the later vectors in turn, lanes across the entries
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int t = 0; t < K; ++t) {
+        const double* xt = Zt + (int64_t)t * L;
+        double nt = 0.0;
+        for (int i = lane; i < L; i += 64) nt = fma(xt[i], xt[i], nt);
+        nt = wave_sum(nt);
+        if (nt > 0.0) {
+          for (int u = t + 1 + wave; u < K; u += kFullThreads / 64) {
+            double* xu = Zt + (int64_t)u * L;
+            double dot = 0.0;
+            for (int i = lane; i < L; i += 64) dot = fma(xu[i], xt[i], dot);
+            const double cf = wave_sum(dot) / nt;
+            for (int i = lane; i < L; i += 64) xu[i] = fma(-cf, xt[i], xu[i]);
+          }
+        }
+        __syncthreads();  // x_{t+1} is final before step t + 1 reads it
+      }
+    }
+    for (int t = wave; t < K; t += kFullThreads / 64) {
+      double* x = Zt + (int64_t)t * L;
+      double nrm = 0.0;
+      for (int i = lane; i < L; i += 64) nrm = fma(x[i], x[i], nrm);
+      nrm = wave_sum(nrm);
+      bad |= !(nrm > 0.0) || !isfinite(nrm);
+      const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = lane; i < L; i += 64) x[i] *= inv;
+    }
+  } else {
   for (int64_t i = tid; i < (int64_t)L * L; i += kFullThreads)
     Zt[i] = (i / L == i % L) ? 1.0 : 0.0;
   __syncthreads();
@@ -298,7 +513,6 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
   __syncthreads();
 
   // ---- 3. the K largest eigenvalues, descending (lower index first on ties)
-  int bad = 0;
   for (int j = tid; j < L; j += kFullThreads) {
     const double dj = d[j];
     bad |= !isfinite(dj);
@@ -309,6 +523,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     }
     if (rank < K) sel[rank] = (double)j;
   }
+  }  // QL path
   bad = __syncthreads_or(bad);
   __syncthreads();
   double* ev = ev_base + job.ev_off;
@@ -433,7 +648,10 @@ hipError_t full_attrs() {
 
 int eig_full_max_L() { return kFullMaxL; }
 
-size_t eig_full_work_elems(int L) { return (size_t)2 * L * L + 4 * (size_t)L + 1; }
+size_t eig_full_work_elems(int L) {
+  return (size_t)eig_full_base_elems(L) +
+         (L >= kInvItMinL ? (size_t)6 * L * (size_t)invit_slots(L) : 0);
+}
 
 hipError_t launch_eig_full(int count, const EigFullJob* jobs_dev, int Lmax, int Kmax,
                            const double* S_base, double* F_base, double* ev_base,
