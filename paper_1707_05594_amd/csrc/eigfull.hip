@@ -49,7 +49,11 @@
 
 namespace tk {
 
-constexpr int kFullThreads = 256;
+constexpr int kFullThreads = 256;  // back-transform
+// reduction, QL / bisection and inverse iteration: 16 waves, so that one CU
+// keeps enough loads in flight for the L^3 passes over the work matrix
+constexpr int kTqThreads = 1024;
+constexpr int kInvItSlots = 512;  // threads that run inverse iteration at once
 constexpr int kFullMaxL = 2048;
 constexpr int kQlMaxSweeps = 60;  // per eigenvalue
 
@@ -61,7 +65,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int w = 0; w < kFullThreads / 64; ++w) s += red[w];
+  for (int w = 0; w < kTqThreads / 64; ++w) s += red[w];
   return s;
 }
 
@@ -74,7 +78,7 @@ __device__ __forceinline__ int block_min(int v, int* red) {
   __syncthreads();
   int r = red[0];
 #pragma unroll
-  for (int w = 1; w < kFullThreads / 64; ++w) r = min(r, red[w]);
+  for (int w = 1; w < kTqThreads / 64; ++w) r = min(r, red[w]);
   return r;
 }
 
@@ -183,16 +187,16 @@ __device__ void tri_solve(int L, const double* __restrict__ u0, const double* __
 __host__ __device__ inline int64_t eig_full_base_elems(int L) {
   return 2 * (int64_t)L * L + 4 * (int64_t)L + 1;
 }
-__host__ __device__ inline int invit_slots(int L) { return L < kFullThreads ? L : kFullThreads; }
+__host__ __device__ inline int invit_slots(int L) { return L < kInvItSlots ? L : kInvItSlots; }
 
 struct FullShared {
-  double red[kFullThreads / 64];
+  double red[kTqThreads / 64];
   double scal[4];
-  int redi[kFullThreads / 64];
+  int redi[kTqThreads / 64];
   int flag, lo;
 };
 
-__global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
+__global__ __launch_bounds__(kTqThreads) void eig_full_tridiag_ql(
     const EigFullJob* __restrict__ jobs, const double* __restrict__ S_base,
     double* __restrict__ ev_base, double* __restrict__ work_base, int* __restrict__ status) {
   extern __shared__ double lds[];  // v, w (L each), rotation cosines, sines (L each)
@@ -216,7 +220,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
   double* cs = lds + 2 * L;
   double* sn = lds + 3 * L;
 
-  for (int64_t i = tid; i < (int64_t)L * L; i += kFullThreads) A[i] = S[i];
+  for (int64_t i = tid; i < (int64_t)L * L; i += kTqThreads) A[i] = S[i];
   __syncthreads();
 
   // ---- 1. Householder reduction to tridiagonal form
@@ -224,7 +228,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     const int m = L - j - 1;  // length of the column below the diagonal
     double* row = A + (int64_t)j * L + j + 1;  // = that column, by symmetry
     double part = 0.0;
-    for (int k = 1 + tid; k < m; k += kFullThreads) part = fma(row[k], row[k], part);
+    for (int k = 1 + tid; k < m; k += kTqThreads) part = fma(row[k], row[k], part);
     const double sigma = block_sum(part, sh.red);
     const double alpha = row[0];
     if (tid == 0) {
@@ -249,16 +253,16 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
       continue;
     }
     const double inv = sh.scal[1];
-    for (int k = tid; k < m; k += kFullThreads) {
+    for (int k = tid; k < m; k += kTqThreads) {
       const double vk = k == 0 ? 1.0 : row[k] * inv;
       v[k] = vk;
     }
     __syncthreads();
-    for (int k = tid; k < m; k += kFullThreads) row[k] = v[k];  // kept for the back-transform
+    for (int k = tid; k < m; k += kTqThreads) row[k] = v[k];  // kept for the back-transform
     // p = tau * A' v over the trailing block A' (rows/columns j+1 ..), column
     // by column through the symmetric rows, which keeps the loads coalesced
     double* Ap = A + (int64_t)(j + 1) * L + (j + 1);
-    for (int i = tid; i < m; i += kFullThreads) {
+    for (int i = tid; i < m; i += kTqThreads) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       int k = 0;
       for (; k + 4 <= m; k += 4) {
@@ -272,13 +276,13 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     }
     __syncthreads();
     double pv = 0.0;
-    for (int k = tid; k < m; k += kFullThreads) pv = fma(w[k], v[k], pv);
+    for (int k = tid; k < m; k += kTqThreads) pv = fma(w[k], v[k], pv);
     const double half = 0.5 * t * block_sum(pv, sh.red);
-    for (int k = tid; k < m; k += kFullThreads) w[k] = w[k] - half * v[k];
+    for (int k = tid; k < m; k += kTqThreads) w[k] = w[k] - half * v[k];
     __syncthreads();
     // A' -= v w^T + w v^T, thread by column: eight rows of its column are
     // loaded together (a row-by-row loop waited one memory latency per row)
-    for (int i = tid; i < m; i += kFullThreads) {
+    for (int i = tid; i < m; i += kTqThreads) {
       const double wi = w[i], vi = v[i];
       double* col = Ap + i;
       int k = 0;
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     double* dl = lds;
     double* el = lds + L;
     double* e2 = lds + 2 * L;
-    for (int i = tid; i < L; i += kFullThreads) {
+    for (int i = tid; i < L; i += kTqThreads) {
       dl[i] = d[i];
       el[i] = e[i];
       e2[i] = e[i] * e[i];
@@ -340,7 +344,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     }
     __syncthreads();
     const double lo = sh.scal[0], hi = sh.scal[1], pivmin = sh.scal[2], tn = sh.scal[3];
-    for (int t = tid; t < K; t += kFullThreads) {
+    for (int t = tid; t < K; t += kTqThreads) {
       const double lam = bisect_eig(dl, e2, L, L - 1 - t, lo, hi, pivmin);
       d[t] = lam;  // d now holds the selected eigenvalues, largest first
       sel[t] = (double)t;
@@ -385,7 +389,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
         for (int i = lane; i < L; i += 64) nt = fma(xt[i], xt[i], nt);
         nt = wave_sum(nt);
         if (nt > 0.0) {
-          for (int u = t + 1 + wave; u < K; u += kFullThreads / 64) {
+          for (int u = t + 1 + wave; u < K; u += kTqThreads / 64) {
             double* xu = Zt + (int64_t)u * L;
             double dot = 0.0;
             for (int i = lane; i < L; i += 64) dot = fma(xu[i], xt[i], dot);
@@ -396,7 +400,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
         __syncthreads();  // x_{t+1} is final before step t + 1 reads it
       }
     }
-    for (int t = wave; t < K; t += kFullThreads / 64) {
+    for (int t = wave; t < K; t += kTqThreads / 64) {
       double* x = Zt + (int64_t)t * L;
       double nrm = 0.0;
       for (int i = lane; i < L; i += 64) nrm = fma(x[i], x[i], nrm);
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
       for (int i = lane; i < L; i += 64) x[i] *= inv;
     }
   } else {
-  for (int64_t i = tid; i < (int64_t)L * L; i += kFullThreads)
+  for (int64_t i = tid; i < (int64_t)L * L; i += kTqThreads)
     Zt[i] = (i / L == i % L) ? 1.0 : 0.0;
   __syncthreads();
 
@@ -416,7 +420,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
   // on that thread's critical path.
   double* dl = lds;
   double* el = lds + L;
-  for (int i = tid; i < L; i += kFullThreads) {
+  for (int i = tid; i < L; i += kTqThreads) {
     dl[i] = d[i];
     el[i] = e[i];
   }
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
       // m: the first index >= l whose off-diagonal entry is negligible (L - 1
       // if none), searched by the whole block
       int mloc = L - 1;
-      for (int i = l + tid; i < L - 1; i += kFullThreads)
+      for (int i = l + tid; i < L - 1; i += kTqThreads)
         if (fabs(el[i]) <= thresh) {
           mloc = i;
           break;
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
       // of Zt are read eight rotations ahead (independent loads in flight
       // together; a batch never reads a row it or a later batch writes).
       if (lo < m) {
-        for (int r = tid; r < L; r += kFullThreads) {
+        for (int r = tid; r < L; r += kTqThreads) {
           double znext = Zt[(int64_t)m * L + r];
           int i = m - 1;
           for (; i - 7 >= lo; i -= 8) {
@@ -509,11 +513,11 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
     }
     if (sh.flag) break;
   }
-  for (int i = tid; i < L; i += kFullThreads) d[i] = dl[i];
+  for (int i = tid; i < L; i += kTqThreads) d[i] = dl[i];
   __syncthreads();
 
   // ---- 3. the K largest eigenvalues, descending (lower index first on ties)
-  for (int j = tid; j < L; j += kFullThreads) {
+  for (int j = tid; j < L; j += kTqThreads) {
     const double dj = d[j];
     bad |= !isfinite(dj);
     int rank = 0;
@@ -527,7 +531,7 @@ __global__ __launch_bounds__(kFullThreads) void eig_full_tridiag_ql(
   bad = __syncthreads_or(bad);
   __syncthreads();
   double* ev = ev_base + job.ev_off;
-  for (int c = tid; c < K; c += kFullThreads) ev[c] = d[(int)sel[c]];
+  for (int c = tid; c < K; c += kTqThreads) ev[c] = d[(int)sel[c]];
   if (tid == 0) {
     status[job.status_idx] = bad ? 2 : (sh.flag ? 1 : 0);
     *done = (bad || sh.flag) ? 0.0 : 1.0;
@@ -660,7 +664,7 @@ hipError_t launch_eig_full(int count, const EigFullJob* jobs_dev, int Lmax, int 
   if (Lmax < 1 || Lmax > kFullMaxL || Kmax < 1) return hipErrorInvalidValue;
   hipError_t e = full_attrs();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(eig_full_tridiag_ql, dim3(count), dim3(kFullThreads),
+  hipLaunchKernelGGL(eig_full_tridiag_ql, dim3(count), dim3(kTqThreads),
                      4 * (size_t)Lmax * sizeof(double), st, jobs_dev, S_base, ev_base, work_base,
                      status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
