@@ -231,24 +231,30 @@ extern "C" int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int com
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if (!(margin >= 0.0 && margin < 1.0)) return fail(TK_EINVAL, "margin outside [0, 1)");
   const Shape& s = plan->shape;
-  const int wdtype = compute == TK_C_FP64 ? TK_F64 : TK_F32;
   const int ntiles = compute == TK_C_FP64 ? 1 : TK_TILE_COUNT;
-  // one feature row per (tree, internal node, tile)
+  // one feature row per (tree, internal node, tile), each node with the
+  // input type and compute mode the engine gives it (the core's path at FP32
+  // in the BF16 modes; BF16 intermediates where the engine stores them)
   std::vector<float> X;
   struct Row {
     int tree, node, tile;
   };
   std::vector<Row> rows;
+  const void* aligned = reinterpret_cast<const void*>((uintptr_t)256);
   for (int r = 0; r < (int)plan->trees.size(); ++r) {
     const auto& nodes = plan->trees[r].nodes;
+    int fold_leaf = 0;
+    std::vector<int> node_compute, out_dt;
+    tree_precisions(s, nodes, tdtype, compute, std::vector<int>(), aligned, &fold_leaf,
+                    &node_compute, &out_dt);
     for (int u = 0; u < (int)nodes.size(); ++u) {
       if (nodes[u].is_leaf) continue;
       int64_t A, L, B;
       view(s, nodes[u].pre_mask, nodes[u].mode, &A, &L, &B);
-      const int in_dt = nodes[u].parent < 0 ? tdtype : wdtype;
+      const int in_dt = nodes[u].parent < 0 ? tdtype : out_dt[nodes[u].parent];
       for (int t = 0; t < ntiles; ++t) {
         float f[TK_FEATURES];
-        features(A, L, B, s.K[nodes[u].mode], in_dt, compute, t, f);
+        features(A, L, B, s.K[nodes[u].mode], in_dt, node_compute[u], t, f);
         X.insert(X.end(), f, f + TK_FEATURES);
         rows.push_back({r, u, t});
       }

@@ -328,6 +328,58 @@ int check_status(tk_ctx* c) {
   return TK_OK;
 }
 
+}  // namespace
+
+void tk::tree_precisions(const Shape& s, const std::vector<tk_node>& nodes, int tdtype,
+                         int compute, const std::vector<int>& tiles, const void* T,
+                         int* fold_leaf, std::vector<int>* node_compute,
+                         std::vector<int>* out_dt) {
+  const int N = s.N;
+  int64_t best = -1;
+  for (int n = 0; n < N; ++n) {
+    const int64_t y = (int64_t)s.card(((1u << N) - 1) & ~(1u << n));
+    if (best < 0 || y < best) {
+      best = y;
+      *fold_leaf = n;
+    }
+  }
+  const int core_compute =
+      (compute == TK_C_BF16 || compute == TK_C_BF16X3) ? TK_C_FP32 : compute;
+  node_compute->assign(nodes.size(), compute);
+  for (size_t u = 0; u < nodes.size(); ++u)
+    if (nodes[u].is_leaf && nodes[u].mode == *fold_leaf)
+      for (int v = (int)u; v >= 0; v = nodes[v].parent) (*node_compute)[v] = core_compute;
+  auto tile = [&](size_t u) { return u < tiles.size() ? tiles[u] : (int)TK_TILE_AUTO; };
+  // intermediates sit at 64-element offsets of the workspace: any 256-byte
+  // aligned address stands for them in the kernels' alignment checks
+  const void* ws = reinterpret_cast<const void*>((uintptr_t)256);
+  const int wdtype = compute == TK_C_FP64 ? TK_F64 : TK_F32;
+  std::vector<char> feeds_leaf(nodes.size(), 0);
+  for (const tk_node& nd : nodes)
+    if (nd.parent >= 0 && nd.is_leaf) feeds_leaf[nd.parent] = 1;
+  // parents before children: a child's kernel choice depends on its input's type
+  out_dt->assign(nodes.size(), wdtype);
+  for (size_t u = 0; u < nodes.size(); ++u) {
+    const tk_node& nd = nodes[u];
+    if (nd.is_leaf || feeds_leaf[u] || (*node_compute)[u] != TK_C_BF16) continue;
+    int64_t A, Lu, B;
+    view(s, nd.pre_mask, nd.mode, &A, &Lu, &B);
+    const int in_dt = nd.parent < 0 ? tdtype : (*out_dt)[nd.parent];
+    bool ok = ttm_bf16_output_ok(in_dt, TK_C_BF16, nd.parent < 0 ? T : ws, A, Lu, B, ws,
+                                 tile(u));
+    for (size_t v = 0; v < nodes.size() && ok; ++v) {
+      if (nodes[v].parent != (int)u) continue;
+      int64_t Av, Lv, Bv;
+      view(s, nodes[v].pre_mask, nodes[v].mode, &Av, &Lv, &Bv);
+      ok = (*node_compute)[v] == TK_C_BF16 &&
+           ttm_bf16_output_ok(TK_BF16, TK_C_BF16, ws, Av, Lv, Bv, ws, tile(v));
+    }
+    if (ok) (*out_dt)[u] = TK_BF16;
+  }
+}
+
+namespace {
+
 // Execution order of the nodes: depth-first, root subtrees in plan order or,
 // with `reverse`, in reverse plan order (each subtree stays depth-first).
 std::vector<int> exec_order(const std::vector<tk_node>& nodes, bool reverse) {
@@ -514,7 +566,6 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   c->node_tile.resize(nodes.size(), TK_TILE_AUTO);
   c->node_off.assign(nodes.size(), 0);
   int64_t ws = 0;
-  int64_t best_leaf = -1;
   for (size_t u = 0; u < nodes.size(); ++u) {
     const tk_node& nd = nodes[u];
     // 64-element (>= 256-byte) alignment keeps the kernels' vector loads aligned
@@ -567,19 +618,9 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
       }
     }
   }
-  // leaf that folds the core: the smallest Y (ties: lowest mode)
-  for (int n = 0; n < N; ++n) {
-    const int64_t y = (int64_t)s.card(((1u << N) - 1) & ~(1u << n));
-    if (best_leaf < 0 || y < best_leaf) {
-      best_leaf = y;
-      c->fold_leaf = n;
-    }
-  }
   c->core_compute = (compute == TK_C_BF16 || compute == TK_C_BF16X3) ? TK_C_FP32 : compute;
-  c->node_compute.assign(nodes.size(), compute);
-  for (size_t u = 0; u < nodes.size(); ++u)
-    if (nodes[u].is_leaf && nodes[u].mode == c->fold_leaf)
-      for (int v = (int)u; v >= 0; v = nodes[v].parent) c->node_compute[v] = c->core_compute;
+  tree_precisions(s, nodes, tdtype, compute, c->node_tile, T_dev, &c->fold_leaf,
+                  &c->node_compute, &c->node_out_dt);
   // direct core chain order: ascending K L / (L - K), modes with K = L last
   c->chain_order.resize(N);
   for (int j = 0; j < N; ++j) c->chain_order[j] = j;
@@ -726,33 +767,6 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   c->node_stream.assign(nodes.size(), 0);
   for (size_t u = 0; u < nodes.size(); ++u)
     c->node_stream[u] = nodes[u].parent < 0 || children[nodes[u].parent] == 1;
-  c->node_out_dt.assign(nodes.size(), -1);
-  for (size_t u0 = 0; u0 < nodes.size(); ++u0) {
-    std::vector<int> up;
-    for (int v = (int)u0; v >= 0 && c->node_out_dt[v] < 0; v = nodes[v].parent) up.push_back(v);
-    for (auto it = up.rbegin(); it != up.rend(); ++it) {
-      const int u = *it;
-      const tk_node& nd = nodes[u];
-      int dt = c->wdtype;
-      if (!nd.is_leaf && !feeds_leaf[u] && c->node_compute[u] == TK_C_BF16) {
-        int64_t A, Lu, B;
-        view(s, nd.pre_mask, nd.mode, &A, &Lu, &B);
-        const void* in = nd.parent < 0 ? c->T : c->wsp(c->node_off[nd.parent]);
-        bool ok = ttm_bf16_output_ok(c->in_dtype_of(u), TK_C_BF16, in, A, Lu, B,
-                                     c->wsp(c->node_off[u]), c->node_tile[u]);
-        for (size_t v = 0; v < nodes.size() && ok; ++v) {
-          if (nodes[v].parent != u) continue;
-          int64_t Av, Lv, Bv;
-          view(s, nodes[v].pre_mask, nodes[v].mode, &Av, &Lv, &Bv);
-          ok = c->node_compute[v] == TK_C_BF16 &&
-               ttm_bf16_output_ok(TK_BF16, TK_C_BF16, c->wsp(c->node_off[u]), Av, Lv, Bv,
-                                  c->wsp(c->node_off[v]), c->node_tile[v]);
-        }
-        if (ok) dt = TK_BF16;
-      }
-      c->node_out_dt[u] = dt;
-    }
-  }
 
   {
     hipError_t e = hipMemcpyAsync(c->jobs, c->jobs_h.data(), sizeof(EigJob) * N,

@@ -63,6 +63,20 @@ struct Tree {
 std::string canonical_string(const std::vector<tk_node>& nodes);
 uint64_t workspace_elements(const std::vector<tk_node>& nodes);
 
+// Precision of every node of a tree as the engine runs it (engine.cpp):
+//   fold_leaf: the leaf whose tensor folds the core (smallest Y, lowest mode);
+//   node_compute[u]: `compute`, except FP32 on the path from the root to the
+//     fold leaf in the BF16 modes (the core is formed at FP32);
+//   out_dt[u]: storage of node u's output: BF16 when u runs the BF16 mode, no
+//     child of u is a leaf, and u and every child have a BF16 kernel for it
+//     (BF16 output and input); else FP32 (FP64 for FP64 compute).
+// T: the tensor's device address (its alignment picks kernels); the
+// intermediates are taken to sit at the engine's 64-element-aligned offsets.
+// tiles: per-node kernel choices (TK_TILE_*), or empty for automatic.
+void tree_precisions(const Shape& s, const std::vector<tk_node>& nodes, int tdtype, int compute,
+                     const std::vector<int>& tiles, const void* T, int* fold_leaf,
+                     std::vector<int>* node_compute, std::vector<int>* out_dt);
+
 }  // namespace tk
 
 struct tk_plan {
