@@ -276,8 +276,12 @@ int hooi_batch_get_factors(tk_batch* b, double* host);
 int hooi_batch_set_factors(tk_batch* b, const double* host);
 /* on = 0: enqueue every iteration eagerly instead of replaying the graph. */
 int hooi_batch_use_graph(tk_batch* b, int on);
-/* Autotuner: times the tree levels with 1, 2, 3 and 4 persistent blocks per
- * CU, keeps the fastest (ms: NULL or 4 floats) and re-captures the graph. */
+/* Autotuner: times a tree pass with 1, 2, 3 and 4 persistent blocks per CU
+ * and keeps the fastest; then, at that grid, times the other body for the
+ * odd-length row nodes (their own persistent launch with the barrier-free
+ * row body, or the shared queue's row body) and keeps the faster; finally
+ * re-captures the graph.  ms: NULL or 5 floats (ms per pass: the four grids,
+ * then the other row body). */
 int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms);
 /* Multiply-adds and algorithmic bytes (inputs read once, outputs written
  * once) of all tree nodes, tree levels and TTM work items. */

@@ -659,7 +659,7 @@ class Batch:
     def tune(self):
         import numpy as np
         bpc = ctypes.c_int()
-        ms = np.zeros(4, dtype=np.float32)
+        ms = np.zeros(5, dtype=np.float32)
         _check(lib().hooi_batch_tune(self._h, ctypes.byref(bpc), ms.ctypes.data_as(_fp)))
         return bpc.value, ms
 

@@ -49,8 +49,10 @@ struct Launch {
   int in_dtype = TK_F32;
   int node0 = 0, item0 = 0, n_items = 0;
   int Lmax = 1;
-  // items of the odd-L row nodes with BF16 input (kGroupedRowsScalar), run by
-  // their own persistent launch after the others: [ritem0, ritem0 + n_ritems)
+  // items of the odd-L row nodes (kGroupedRowsScalar), right after the others:
+  // [ritem0, ritem0 + n_ritems).  The autotuner decides whether they join the
+  // shared queue (one launch over both ranges, the shared kernel's row body)
+  // or run in a persistent launch of their own (the barrier-free row body).
   int ritem0 = 0, n_ritems = 0, rLmax = 1;
 };
 
@@ -73,6 +75,10 @@ struct tk_batch {
   hipEvent_t ev_fork = nullptr, ev_join[kAux] = {};
   int ncu = 256;
   int blocks_per_cu = 4;
+  // odd-length row items in a launch of their own (true) or in the shared
+  // queue; set by hooi_batch_tune from measured passes.  Untuned default:
+  // separate for BF16 storage (the shared body's 2-byte loads are slow).
+  bool split_rows = false;
 
   // factor layout: tensor i, mode n at fofs[i][n] (elements)
   std::vector<std::vector<int64_t>> fofs, sofs, kofs;
@@ -172,6 +178,10 @@ int enqueue_pass(tk_batch* b) {
   // items hold indices into the whole node table; each launch has two queue
   // heads (its other items, then its odd-L row items)
   auto run = [&](const Launch& l, int q, bool stream_in) -> hipError_t {
+    if (!b->split_rows)  // one queue over both ranges (they are adjacent)
+      return launch_ttm_grouped(l.in_dtype, b->ttm_nodes, b->ttm_items + l.item0,
+                                l.n_items + l.n_ritems, b->counters + 2 * q,
+                                std::max(l.Lmax, l.rLmax), grid_blocks(b), stream_in, b->st);
     hipError_t e = launch_ttm_grouped(l.in_dtype, b->ttm_nodes, b->ttm_items + l.item0,
                                       l.n_items, b->counters + 2 * q, l.Lmax, grid_blocks(b),
                                       stream_in, b->st);
@@ -263,6 +273,7 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
   };
   b->count = count;
   b->tdtype = tdtype;
+  b->split_rows = tdtype == TK_BF16;
   b->user = (hipStream_t)stream;
   {
     int dev = 0;
@@ -394,12 +405,7 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
     const int idx = (int)nd_h.size();
     nd_h.push_back(d);
     node_tiles.push_back(tiles);
-    // BF16 odd-length rows take the separate row launch (2-byte loads in the
-    // shared body measured 35.3 ms per batch invocation, 27.4 with it); FP32
-    // ones stay in the shared queue, where they interleave with the other
-    // bodies (the separate launch measured 23.5 ms against 22.4)
-    const bool sep = d.path == kGroupedRowsScalar && in_bytes == 2;
-    auto& dst = sep ? it_rows : it_h;
+    auto& dst = d.path == kGroupedRowsScalar ? it_rows : it_h;
     for (int64_t t = 0; t < tiles; ++t) dst.push_back(make_int2(idx, (int)t));
   };
   // close a launch: its odd-L row items go after its other items
@@ -429,7 +435,7 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
                  s.K[nd.mode]);
         b->tree_bytes += (uint64_t)nd.in_card * (nd.parent < 0 && tdtype == TK_BF16 ? 2 : 4) +
                          (uint64_t)nd.out_card * 4;
-        if (nd_h.back().path == kGroupedRowsScalar && in_bytes == 2)
+        if (nd_h.back().path == kGroupedRowsScalar)
           l.rLmax = std::max<int>(l.rLmax, (int)Ln);
         else
           l.Lmax = std::max<int>(l.Lmax, (int)Ln);
@@ -454,7 +460,10 @@ extern "C" int hooi_batch_init(int count, const int* N, const int64_t* L, const 
         view(s, nd.pre_mask, m, &A, &Ln, &B);
         add_node(b->ws + node_off[i][nd.parent], 4, b->core + core_off_h[i],
                  b->Fc + b->fofs[i][m], A, Ln, B, s.K[m]);
-        f.Lmax = std::max<int>(f.Lmax, (int)Ln);
+        if (nd_h.back().path == kGroupedRowsScalar)
+          f.rLmax = std::max<int>(f.rLmax, (int)Ln);
+        else
+          f.Lmax = std::max<int>(f.Lmax, (int)Ln);
       }
     }
     close_launch(f);
@@ -796,25 +805,32 @@ extern "C" int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms) {
   clear_error();
   if (!b) return fail(TK_EINVAL, "batch is null");
   Handoff handoff(b);
-  static const int cand[4] = {1, 2, 3, 4};  // the grouped kernel holds 3 blocks per CU
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TK_HIP(hipEventCreate(&e0));
   TK_HIP(hipEventCreate(&e1));
+  // average time of three passes in the current configuration (after one
+  // untimed pass at it)
+  auto time_pass = [&](float* t) -> int {
+    int rc = enqueue_pass(b);
+    hipError_t e = rc ? hipSuccess : hipEventRecord(e0, b->st);
+    for (int r = 0; r < 3 && rc == TK_OK && e == hipSuccess; ++r) rc = enqueue_pass(b);
+    if (rc == TK_OK && e == hipSuccess) e = hipEventRecord(e1, b->st);
+    if (rc == TK_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    if (rc == TK_OK && e == hipSuccess) e = hipEventElapsedTime(t, e0, e1);
+    if (rc == TK_OK && e != hipSuccess) rc = fail(TK_EDEVICE, "tuning failed: %s", hipGetErrorString(e));
+    *t /= 3.f;
+    return rc;
+  };
+  // 1. blocks per CU (the grouped kernel holds 3 per CU; 4 oversubscribes)
+  static const int cand[4] = {1, 2, 3, 4};
   float best = 0.f;
   int pick = b->blocks_per_cu;
   int rc = TK_OK;
   for (int c = 0; c < 4 && rc == TK_OK; ++c) {
     b->blocks_per_cu = cand[c];
-    rc = enqueue_pass(b);  // warm-up at this size
-    hipError_t e = rc ? hipSuccess : hipEventRecord(e0, b->st);
-    for (int r = 0; r < 3 && rc == TK_OK && e == hipSuccess; ++r) rc = enqueue_pass(b);
-    if (rc == TK_OK && e == hipSuccess) e = hipEventRecord(e1, b->st);
-    if (rc == TK_OK && e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.f;
-    if (rc == TK_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-    if (rc == TK_OK && e != hipSuccess) rc = fail(TK_EDEVICE, "tuning failed: %s", hipGetErrorString(e));
+    rc = time_pass(&t);
     if (rc == TK_OK) {
-      t /= 3.f;
       if (ms) ms[c] = t;
       if (c == 0 || t < best) {
         best = t;
@@ -822,12 +838,26 @@ extern "C" int hooi_batch_tune(tk_batch* b, int* blocks_per_cu, float* ms) {
       }
     }
   }
+  // 2. the odd-length rows' body: the shared queue's or the separate launch's
+  bool split_pick = b->split_rows;
+  if (rc == TK_OK) {
+    b->blocks_per_cu = pick;
+    b->split_rows = !b->split_rows;
+    float t = 0.f;
+    rc = time_pass(&t);
+    if (rc == TK_OK && t < best) {
+      best = t;
+      split_pick = b->split_rows;
+    }
+    if (ms) ms[4] = t;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  b->split_rows = split_pick;
   if (rc) return rc;
   b->blocks_per_cu = pick;
   if (blocks_per_cu) *blocks_per_cu = pick;
-  if (b->use_graph) return build_graph(b);  // re-capture with the chosen grid
+  if (b->use_graph) return build_graph(b);  // re-capture with the chosen configuration
   return TK_OK;
 }
 

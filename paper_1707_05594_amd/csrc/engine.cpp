@@ -575,21 +575,19 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
     if (!nd.is_leaf) ws = std::max<int64_t>(ws, base + (int64_t)nd.out_card);
   }
   // both root children in one pass over T, when the plan asks for it
-  // (TK_TILE_PAIR on both root nodes, as tk_plan_learned sets it) or with
-  // TK_ROOT_PAIR=1: FP32 storage and compute and a shape a pair kernel takes;
+  // (TK_TILE_PAIR on both root nodes, as tk_plan_learned or tk_plan_set_tiles
+  // set it), with FP32 storage and compute and a shape a pair kernel takes;
   // the second child's subtree moves past the first's in the workspace.
   // Otherwise the root nodes run their own kernels (TK_TILE_AUTO).
   {
     std::vector<int> roots;
     for (size_t u = 0; u < nodes.size(); ++u)
       if (nodes[u].parent < 0) roots.push_back((int)u);
-    const char* env = getenv("TK_ROOT_PAIR");
-    const bool forced = env && atoi(env) == 1;
     bool asked = false;
     for (int u : roots) asked = asked || c->node_tile[u] == TK_TILE_PAIR;
     for (int u : roots)
       if (c->node_tile[u] == TK_TILE_PAIR) c->node_tile[u] = TK_TILE_AUTO;
-    if ((asked || forced) && roots.size() == 2 && !nodes[roots[0]].is_leaf &&
+    if (asked && roots.size() == 2 && !nodes[roots[0]].is_leaf &&
         !nodes[roots[1]].is_leaf && tdtype == TK_F32 && compute == TK_C_FP32 &&
         c->node_tile[roots[0]] == TK_TILE_AUTO && c->node_tile[roots[1]] == TK_TILE_AUTO) {
       int up = roots[0], uq = roots[1];
