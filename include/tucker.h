@@ -54,6 +54,7 @@ extern "C" {
 #define TK_F64 0
 #define TK_F32 1
 #define TK_BF16 2
+#define TK_F16 3  /* IEEE half; FP32 compute only (each value exact in FP32) */
 
 /* arithmetic of the TTM and Gram kernels.  The eigensolver, the factor
  * orthonormalisation, norms and the error are FP64 in every mode. */
@@ -167,7 +168,9 @@ int tk_plan_grids(const tk_plan* plan, int rank, int64_t P, int kind, int* root_
  *   plan : tree to execute (NULL: the DP optimum).  Must have been built for
  *          the same (N, L, K); its selected rank is copied, the plan may be freed.
  *   compute: TK_C_*.  Supported: F64 storage with TK_C_FP64; F32 or BF16
- *          storage with TK_C_FP32, TK_C_BF16, TK_C_BF16X3.  In the BF16
+ *          storage with TK_C_FP32, TK_C_BF16, TK_C_BF16X3; F16 storage with
+ *          TK_C_FP32 only (every half value is exact in FP32, so the tree
+ *          runs the FP32 kernels converting on load; else TK_EUNSUPPORTED).  In the BF16
  *          modes the TTMs that form the core (the tree path to the leaf
  *          that folds it, and the direct core chain) run at FP32: the error
  *          is ||T||^2 - ||G||^2, so ||G||^2 needs more than BF16 accuracy.
@@ -363,7 +366,8 @@ int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute, doubl
 
 /* TTM node (Sec. 2.1): with In viewed as [A, L, B] row-major,
  *   Out[a, k, b] = sum_l F[l, k] * In[a, l, b],  0 <= k < K.
- * in_dtype: TK_F64/TK_F32/TK_BF16 element type of In.  F: device, L x K
+ * in_dtype: TK_F64/TK_F32/TK_BF16/TK_F16 element type of In (TK_F16 with
+ * TK_C_FP32 only, else TK_EUNSUPPORTED).  F: device, L x K
  * row-major FP64 when compute == TK_C_FP64, else FP32.  Out: device,
  * [A, K, B] of FP64 (compute FP64) or FP32.  K <= 4096; L <= 512 for
  * TK_C_FP64, L <= 2048 otherwise.  In and Out must not overlap.
@@ -393,8 +397,9 @@ int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp
 
 /* Gram (Sec. 5): with Y viewed as [A, L, B], S[i, j] = sum_{a,b} Y[a,i,b] Y[a,j,b],
  * written as a full symmetric L x L FP64 matrix to device memory S.
- * in_dtype: TK_F64 (FP64 arithmetic) or TK_F32 (FP32 products, FP64 sums of
- * fixed-size column blocks, fixed order: deterministic).  L <= 1024. */
+ * in_dtype: TK_F64 (FP64 arithmetic), or TK_F32, TK_BF16 or TK_F16 (every
+ * entry widened exactly to FP64, FP64 products and sums of fixed-size column
+ * blocks in a fixed order: deterministic).  L <= 1024. */
 int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_t B, double* S,
             void* stream);
 

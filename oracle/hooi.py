@@ -34,7 +34,7 @@ import numpy as np
 # Sec. 2.1: tensor basics
 # --------------------------------------------------------------------------
 def as_f64(T_stored: np.ndarray, dtype: str) -> np.ndarray:
-    """Exact float64 upcast of a stored tensor ("f64", "f32" or "bf16" bits)."""
+    """Exact float64 upcast of a stored tensor ("f64", "f32", "f16" or "bf16" bits)."""
     if dtype == "bf16":
         b = np.asarray(T_stored, dtype=np.uint16)
         return (b.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)

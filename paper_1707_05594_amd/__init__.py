@@ -18,14 +18,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtucker.so")
 
 TK_OK, TK_EINVAL, TK_ENOMEM, TK_EDEVICE, TK_ENUMERIC, TK_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-TK_F64, TK_F32, TK_BF16 = 0, 1, 2
+TK_F64, TK_F32, TK_BF16, TK_F16 = 0, 1, 2, 3
 TK_C_FP64, TK_C_FP32, TK_C_BF16, TK_C_BF16X3 = 0, 1, 2, 3
 TREE_KINDS = {"dp": 0, "chain": 1, "chain_k": 2, "chain_h": 3, "balanced": 4}
 TK_TILE_AUTO, TK_TILE_STAGED, TK_TILE_SPLITK, TK_TILE_COUNT = 0, 1, 2, 3
 TK_TILE_PAIR = 3
 TK_FEATURES = 13
 COMPUTE = {"fp64": TK_C_FP64, "fp32": TK_C_FP32, "bf16": TK_C_BF16, "bf16x3": TK_C_BF16X3}
-DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16}
+DTYPES = {"f64": TK_F64, "f32": TK_F32, "bf16": TK_BF16, "f16": TK_F16}
 MAX_MODES = 12
 
 
@@ -277,7 +277,8 @@ def _torch():
 
 def _dtype_code(t):
     torch = _torch()
-    m = {torch.float64: TK_F64, torch.float32: TK_F32, torch.bfloat16: TK_BF16}
+    m = {torch.float64: TK_F64, torch.float32: TK_F32, torch.bfloat16: TK_BF16,
+         torch.float16: TK_F16}
     if t.dtype not in m:
         raise TypeError(f"unsupported dtype {t.dtype}")
     return m[t.dtype]

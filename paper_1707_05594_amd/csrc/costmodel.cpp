@@ -96,7 +96,7 @@ extern "C" int tk_ttm_features(int64_t A, int64_t L, int64_t B, int64_t K, int i
   clear_error();
   if (!out) return fail(TK_EINVAL, "out is null");
   if (A < 1 || L < 1 || B < 1 || K < 1) return fail(TK_EINVAL, "sizes must be >= 1");
-  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (in_dtype < TK_F64 || in_dtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
   if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if (tile < 0 || tile >= TK_TILE_COUNT) return fail(TK_EINVAL, "unknown tile %d", tile);
@@ -110,7 +110,7 @@ extern "C" int tk_pair_features(int64_t A, int64_t Lp, int64_t M, int64_t Lq, in
   if (!out) return fail(TK_EINVAL, "out is null");
   if (A < 1 || Lp < 1 || M < 1 || Lq < 1 || B < 1 || Kp < 1 || Kq < 1)
     return fail(TK_EINVAL, "sizes must be >= 1");
-  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (in_dtype < TK_F64 || in_dtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
   if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   pair_features(A, Lp, M, Lq, B, Kp, Kq, in_dtype, compute, out);
@@ -226,7 +226,7 @@ extern "C" int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int com
                                double margin, int* chosen, double* predicted_ms) {
   clear_error();
   if (!plan || !model) return fail(TK_EINVAL, "null pointer");
-  if (tdtype < TK_F64 || tdtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (tdtype < TK_F64 || tdtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
   if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if (!(margin >= 0.0 && margin < 1.0)) return fail(TK_EINVAL, "margin outside [0, 1)");

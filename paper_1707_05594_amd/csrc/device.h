@@ -37,6 +37,12 @@ struct Elem<uint16_t> {
   __device__ __forceinline__ static float to_f32(uint16_t v) { return bf16_to_f32(v); }
   __device__ __forceinline__ static double to_f64(uint16_t v) { return (double)bf16_to_f32(v); }
 };
+// IEEE half storage (TK_F16): every value is exact in FP32
+template <>
+struct Elem<_Float16> {
+  __device__ __forceinline__ static float to_f32(_Float16 v) { return (float)v; }
+  __device__ __forceinline__ static double to_f64(_Float16 v) { return (double)(float)v; }
+};
 
 typedef unsigned int u2v __attribute__((ext_vector_type(2)));
 
@@ -61,6 +67,20 @@ __device__ __forceinline__ f4 load4_f32(const uint16_t* p) {
   r[1] = __uint_as_float(v[0] & 0xFFFF0000u);
   r[2] = __uint_as_float(v[1] << 16);
   r[3] = __uint_as_float(v[1] & 0xFFFF0000u);
+  return r;
+}
+template <bool NT = false>
+__device__ __forceinline__ f4 load4_f32(const _Float16* p) {
+  u2v v;
+  if constexpr (NT)
+    v = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+  else
+    v = *reinterpret_cast<const u2v*>(p);
+  f4 r;
+  r[0] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[0] & 0xFFFFu));
+  r[1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[0] >> 16));
+  r[2] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[1] & 0xFFFFu));
+  r[3] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[1] >> 16));
   return r;
 }
 

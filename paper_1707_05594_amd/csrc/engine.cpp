@@ -528,11 +528,13 @@ extern "C" int hooi_init(int N, const int64_t* L, const int64_t* K, int tdtype, 
   Shape s;
   if (int rc = make_shape(N, L, K, &s)) return rc;
   if (!T_dev) return fail(TK_EINVAL, "T_dev is null");
-  if (tdtype < TK_F64 || tdtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (tdtype < TK_F64 || tdtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
   if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if ((tdtype == TK_F64) != (compute == TK_C_FP64))
     return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
+  if (tdtype == TK_F16 && compute != TK_C_FP32)
+    return fail(TK_EUNSUPPORTED, "FP16 storage pairs with FP32 compute only");
   const int maxL = std::min(compute == TK_C_FP64 ? 512 : ttm_max_L(), eig_full_max_L());
   for (int j = 0; j < N; ++j)
     if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
@@ -851,11 +853,13 @@ extern "C" int hooi_init_sthosvd(int N, const int64_t* L, const int64_t* K, int 
   Shape s;
   if (int rc = make_shape(N, L, K, &s)) return rc;
   if (!T_dev) return fail(TK_EINVAL, "T_dev is null");
-  if (tdtype < TK_F64 || tdtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (tdtype < TK_F64 || tdtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
   if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
   if ((tdtype == TK_F64) != (compute == TK_C_FP64))
     return fail(TK_EUNSUPPORTED, "FP64 storage pairs with FP64 compute only");
+  if (tdtype == TK_F16 && compute != TK_C_FP32)
+    return fail(TK_EUNSUPPORTED, "FP16 storage pairs with FP32 compute only");
   const int maxL = std::min(compute == TK_C_FP64 ? 512 : ttm_max_L(), eig_full_max_L());
   for (int j = 0; j < N; ++j)
     if (s.L[j] > maxL) return fail(TK_EUNSUPPORTED, "L[%d]=%lld exceeds %d", j, (long long)s.L[j], maxL);
@@ -1217,13 +1221,15 @@ extern "C" int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   clear_error();
   if (!in || !F || !out) return fail(TK_EINVAL, "null pointer");
   if (A < 1 || L < 1 || B < 1 || K < 1) return fail(TK_EINVAL, "sizes must be >= 1");
-  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (in_dtype < TK_F64 || in_dtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
   if (compute == TK_C_FP64) {
     if (in_dtype != TK_F64) return fail(TK_EUNSUPPORTED, "FP64 compute needs FP64 input");
     if (L > 512) return fail(TK_EUNSUPPORTED, "FP64 TTM supports L <= 512");
   } else if (compute >= TK_C_FP32 && compute <= TK_C_BF16X3) {
     if (in_dtype == TK_F64)
-      return fail(TK_EUNSUPPORTED, "compute mode %d takes F32/BF16 input", compute);
+      return fail(TK_EUNSUPPORTED, "compute mode %d takes F32/BF16/F16 input", compute);
+    if (in_dtype == TK_F16 && compute != TK_C_FP32)
+      return fail(TK_EUNSUPPORTED, "FP16 input takes FP32 compute only");
     if (L > ttm_max_L()) return fail(TK_EUNSUPPORTED, "L=%lld exceeds %d", (long long)L, ttm_max_L());
   } else {
     return fail(TK_EINVAL, "unknown compute mode %d", compute);
@@ -1256,7 +1262,7 @@ extern "C" int tk_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_
   if (!Y || !S) return fail(TK_EINVAL, "null pointer");
   if (A < 1 || L < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
   if (L > 1024) return fail(TK_EUNSUPPORTED, "L > 1024");
-  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (in_dtype < TK_F64 || in_dtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
   const size_t gp = gram_workspace_elems(L, A * B);
   double* part = nullptr;
   if (int rc = dalloc((void**)&part, sizeof(double) * gp)) return rc;

@@ -373,6 +373,9 @@ hipError_t launch_gram(int in_dtype, const void* Y, int64_t A, int64_t L, int64_
   else if (in_dtype == TK_F32)
     hipLaunchKernelGGL(gram_partial<float>, grid, dim3(256), 0, st, (const float*)Y, (int)L, B, C,
                        g.cchunk, g.T, g.npairs, part);
+  else if (in_dtype == TK_F16)
+    hipLaunchKernelGGL(gram_partial<_Float16>, grid, dim3(256), 0, st, (const _Float16*)Y,
+                       (int)L, B, C, g.cchunk, g.T, g.npairs, part);
   else
     hipLaunchKernelGGL(gram_partial<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)Y,
                        (int)L, B, C, g.cchunk, g.T, g.npairs, part);
@@ -430,7 +433,7 @@ extern "C" int tk_gram_noalloc(int in_dtype, const void* Y, int64_t A, int64_t L
   if (!Y || !S) return fail(TK_EINVAL, "null pointer");
   if (A < 1 || L < 1 || B < 1) return fail(TK_EINVAL, "sizes must be >= 1");
   if (L > 1024) return fail(TK_EUNSUPPORTED, "L > 1024");
-  if (in_dtype < TK_F64 || in_dtype > TK_BF16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
+  if (in_dtype < TK_F64 || in_dtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", in_dtype);
   const int64_t C = A * B;
   GramGeom g = gram_geom(L, C);
   const size_t per_chunk = (size_t)g.npairs * kGT * kGT;
@@ -457,6 +460,9 @@ extern "C" int tk_gram_noalloc(int in_dtype, const void* Y, int64_t A, int64_t L
   else if (in_dtype == TK_F32)
     hipLaunchKernelGGL(gram_partial<float>, grid, dim3(256), 0, st, (const float*)Y, (int)L, B, C,
                        g.cchunk, g.T, g.npairs, part);
+  else if (in_dtype == TK_F16)
+    hipLaunchKernelGGL(gram_partial<_Float16>, grid, dim3(256), 0, st, (const _Float16*)Y,
+                       (int)L, B, C, g.cchunk, g.T, g.npairs, part);
   else
     hipLaunchKernelGGL(gram_partial<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)Y,
                        (int)L, B, C, g.cchunk, g.T, g.npairs, part);

@@ -53,6 +53,9 @@ hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* part, doubl
   else if (dtype == TK_F32)
     hipLaunchKernelGGL(sumsq_partial<float>, dim3(blocks), dim3(256), 0, st, (const float*)x, n,
                        part);
+  else if (dtype == TK_F16)
+    hipLaunchKernelGGL(sumsq_partial<_Float16>, dim3(blocks), dim3(256), 0, st,
+                       (const _Float16*)x, n, part);
   else
     hipLaunchKernelGGL(sumsq_partial<uint16_t>, dim3(blocks), dim3(256), 0, st,
                        (const uint16_t*)x, n, part);
@@ -185,6 +188,9 @@ hipError_t launch_residual(int dtype, const void* Tt, const double* Zp, const do
   else if (dtype == TK_F32)
     hipLaunchKernelGGL(residual_partial<float>, dim3(blocks), dim3(256), 0, st, (const float*)Tt,
                        Zp, F0, L0, K0, R, part);
+  else if (dtype == TK_F16)
+    hipLaunchKernelGGL(residual_partial<_Float16>, dim3(blocks), dim3(256), 0, st,
+                       (const _Float16*)Tt, Zp, F0, L0, K0, R, part);
   else
     hipLaunchKernelGGL(residual_partial<uint16_t>, dim3(blocks), dim3(256), 0, st,
                        (const uint16_t*)Tt, Zp, F0, L0, K0, R, part);

@@ -1701,6 +1701,7 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
                              (double*)out, st);
   }
   if (compute == TK_C_BF16 || compute == TK_C_BF16X3) {
+    if (in_dtype == TK_F16) return hipErrorInvalidValue;  // FP16 storage: FP32 compute only
     const bool x3 = compute == TK_C_BF16X3;
     const bool ob = out_dtype == TK_BF16;
     if (in_dtype == TK_F32)
@@ -1712,6 +1713,10 @@ hipError_t launch_ttm(int in_dtype, int compute, const void* in, int64_t A, int6
   if (in_dtype == TK_F32)
     return launch_f32<float>((const float*)in, A, (int)L, B, (const float*)F, (int)K,
                              (float*)out, stream_in, tile, st);
+  // FP32 compute on FP16 input: the FP32 kernels, converting on load
+  if (in_dtype == TK_F16)
+    return launch_f32<_Float16>((const _Float16*)in, A, (int)L, B, (const float*)F, (int)K,
+                                (float*)out, stream_in, tile, st);
   // FP32 compute on BF16 input: on wide grids that fill the chip, BF16 MFMAs
   // with the factor split exactly into three bfloat16 terms (the products of
   // bfloat16 pairs are exact in FP32, so this matches an FP32 MFMA chain up

@@ -163,8 +163,8 @@ def planted(L, K, *, noise: float, noise_kind: str = "rel", core: str = "normal"
             dtype: str = "f64", cfg: int = 0, idx: int = 0):
     """Planted Tucker tensor plus noise, rounded to the storage dtype.
 
-    Returns (T_stored, info) where T_stored is float64/float32 for "f64"/"f32"
-    and uint16 bfloat16 bit patterns for "bf16"; info holds the planted core
+    Returns (T_stored, info) where T_stored is float64/float32/float16 for
+    "f64"/"f32"/"f16" and uint16 bfloat16 bit patterns for "bf16"; info holds the planted core
     and factors (float64) and the noise scale actually applied.
     """
     L = tuple(int(x) for x in L)
@@ -198,6 +198,8 @@ def planted(L, K, *, noise: float, noise_kind: str = "rel", core: str = "normal"
         scale = 0.0
     if dtype == "bf16":
         Ts = round_to_bf16_bits(X)
+    elif dtype == "f16":
+        Ts = X.astype(np.float16)  # IEEE round to nearest even
     elif dtype in ("f32", "f64"):
         Ts = X
     else:

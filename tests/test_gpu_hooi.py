@@ -70,6 +70,8 @@ CASES = [
     ((12, 11, 10, 9, 8), (3, 3, 2, 2, 4), "f32", "fp32", 1e-5),
     ((16, 12, 10, 8, 6, 4), (4, 4, 3, 3, 2, 2), "f32", "fp32", 1e-5),
     ((20, 20, 20, 20, 20), (4, 4, 4, 4, 4), "bf16", "fp32", 1e-5),
+    ((20, 20, 20, 20, 20), (4, 4, 4, 4, 4), "f16", "fp32", 1e-5),
+    ((24, 20, 16, 12), (4, 5, 3, 6), "f16", "fp32", 1e-5),
     ((40, 33, 17), (6, 5, 7), "f64", "fp64", 1e-10),
     # reduced precision, bounds per leaf against the exact chain: bf16x3 1e-4;
     # BF16 1.5e-2 for up to five rounded TTMs on the path to a leaf
@@ -130,6 +132,34 @@ def test_fp32_iterations_match_oracle():
     for n in range(4):
         assert subspace_dist(ctx.factor(n), Fo[n]) < 1e-4
     assert abs(ctx.error_explicit() - errs_o[-1]) < 1e-3 * errs_o[-1]
+
+
+def test_f16_storage_iterations_match_oracle():
+    """IEEE half storage, FP32 compute: the oracle runs in FP64 on the same
+    stored values (exact in FP32), so the FP32 bars of the FP32-storage test
+    hold."""
+    L, K = (30, 28, 26, 24), (5, 4, 6, 3)
+    T, _ = synth.planted(L, K, noise=1e-3, noise_kind="rel", dtype="f16", cfg=71)
+    T64 = O.as_f64(T, "f16")
+    print("f16 storage, fp32 HOOI 30x28x26x24", flush=True)
+    ctx = tk.hooi_init(_device_T(T, "f16"), K, compute="fp32")
+    errs = ctx.iterate(4)
+    Fo, Go, errs_o = O.hooi(T64, K, 4)
+    print(f"errors gpu {errs} oracle {errs_o}", flush=True)
+    for e, eo in zip(errs, errs_o):
+        assert abs(e * e - eo * eo) < 5e-7
+    for n in range(4):
+        assert subspace_dist(ctx.factor(n), Fo[n]) < 1e-4
+    assert abs(ctx.error_explicit() - errs_o[-1]) < 1e-3 * errs_o[-1]
+
+
+@pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
+def test_f16_storage_rejects_bf16_compute(compute):
+    T, _ = synth.planted((8, 8, 8), (2, 2, 2), noise=0.0, dtype="f16", cfg=71)
+    with pytest.raises(tk.TuckerError):
+        tk.hooi_init(_device_T(T, "f16"), (2, 2, 2), compute=compute)
+    with pytest.raises(tk.TuckerError):
+        tk.hooi_init(_device_T(T, "f16"), (2, 2, 2), compute=compute, init="sthosvd")
 
 
 @pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
@@ -255,6 +285,7 @@ def test_ranks_above_subspace_block_limit(dtype, compute):
     ((40, 33, 17), (6, 5, 7), "f64", "fp64", None),
     ((30, 28, 26, 24), (5, 4, 6, 3), "f64", "fp64", (2, 0, 3, 1)),
     ((48, 40, 36, 32), (6, 5, 4, 4), "f32", "fp32", None),
+    ((36, 30, 28, 22), (5, 6, 4, 3), "f16", "fp32", (1, 3, 0, 2)),
     ((24, 20, 16, 12, 10), (4, 5, 3, 6, 2), "bf16", "bf16x3", (4, 3, 2, 1, 0)),
 ])
 def test_sthosvd_start_matches_oracle(L, K, dtype, compute, order):

@@ -98,6 +98,34 @@ def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
                        ttm_tol(L, "fp32", bf16_input=True), f"ttm bf16->fp32 {A}x{L}x{B} K={K}")
 
 
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES)
+def test_ttm_f16_storage_fp32_compute(A, L, B, K):
+    """IEEE half storage: every value is exact in FP32, so the FP32 kernels
+    (converting on load) meet the FP32 bound on the stored values."""
+    torch, dev = torch_dev()
+    print(f"ttm f16 A={A} L={L} B={B} K={K}", flush=True)
+    g = np.random.default_rng(11 + A + L + B + K)
+    Xh = g.standard_normal((A, L, B)).astype(np.float16)
+    F = g.standard_normal((L, K)).astype(np.float32)
+    out = torch.full((A, K, B), float("nan"), dtype=torch.float32, device=dev)
+    tk.ttm(torch.from_numpy(Xh).to(dev), A, L, B, to_dev(F), K, out)
+    torch.cuda.synchronize()
+    X64, F64 = O.as_f64(Xh, "f16"), F.astype(np.float64)
+    ref = O.ttm(X64, F64.T, 1)
+    assert_elementwise(out.cpu().numpy(), ref, abs_ttm(X64, F64.T, 1), ttm_tol(L, "fp32"),
+                       f"ttm f16->fp32 {A}x{L}x{B} K={K}")
+
+
+@pytest.mark.parametrize("compute", ["bf16", "bf16x3"])
+def test_ttm_f16_storage_rejects_bf16_compute(compute):
+    torch, dev = torch_dev()
+    x = torch.zeros((4, 8, 4), dtype=torch.float16, device=dev)
+    F = torch.zeros((8, 2), dtype=torch.float32, device=dev)
+    out = torch.empty((4, 2, 4), dtype=torch.float32, device=dev)
+    with pytest.raises(tk.TuckerError):
+        tk.ttm(x, 4, 8, 4, F, 2, out, compute=compute)
+
+
 def _bf16_mfma_path(A, L, B):
     """Nodes the BF16 kernels take: wide nodes whose 1024-column grid fills the
     chip (256 blocks), and rows with L % 4 == 0.  Others run FP32 kernels (the
@@ -190,7 +218,8 @@ def test_ttm_identity_factor_copies_input():
                                          # ragged last column chunk; B = 1 from BF16
                                          (200, 20, 400, "f32"), (2, 1, 50, "f32"),
                                          (1, 65, 12345, "f32"), (7, 17, 1, "bf16"),
-                                         (300, 33, 1, "f64")])
+                                         (300, 33, 1, "f64"), (5, 64, 33, "f16"),
+                                         (1, 130, 999, "f16")])
 def test_gram(A, L, B, dtype):
     torch, dev = torch_dev()
     print(f"gram A={A} L={L} B={B} {dtype}", flush=True)
@@ -203,6 +232,10 @@ def test_gram(A, L, B, dtype):
         bits = synth.round_to_bf16_bits(Y.astype(np.float32))
         Yd = torch.from_numpy(bits.view(np.int16)).view(torch.bfloat16).to(dev)
         Y64 = O.as_f64(bits, "bf16")
+    elif dtype == "f16":
+        Yh = Y.astype(np.float16)
+        Yd = torch.from_numpy(Yh).to(dev)
+        Y64 = O.as_f64(Yh, "f16")
     else:
         Yd = to_dev(Y)
         Y64 = Y

@@ -175,3 +175,11 @@ def test_hooi_init_validates_before_touching_the_device():
     assert lib.hooi_init(3, Lc, Kc, tk.TK_F32, ctypes.c_void_p(16), plan.handle, tk.TK_C_FP32,
                          None, None, ctypes.byref(h)) == tk.TK_EINVAL
     assert "another shape" in lib.tk_last_error().decode()
+    # FP16 storage pairs with FP32 compute only; an unknown storage code is rejected
+    for comp in (tk.TK_C_BF16, tk.TK_C_BF16X3):
+        assert lib.hooi_init(3, Lc, Kc, tk.TK_F16, ctypes.c_void_p(16), None, comp, None, None,
+                             ctypes.byref(h)) == tk.TK_EUNSUPPORTED
+        assert lib.hooi_init_sthosvd(3, Lc, Kc, tk.TK_F16, ctypes.c_void_p(16), None, comp,
+                                     None, None, ctypes.byref(h)) == tk.TK_EUNSUPPORTED
+    assert lib.hooi_init(3, Lc, Kc, tk.TK_F16 + 1, ctypes.c_void_p(16), None, tk.TK_C_FP32,
+                         None, None, ctypes.byref(h)) == tk.TK_EINVAL
