@@ -49,13 +49,17 @@ void enum_grids(int64_t P, int N, std::vector<int64_t>& cur, std::vector<std::ve
   }
 }
 
-uint64_t binom(uint64_t n, uint64_t k) {
+// C(n, k); false when it exceeds 2^64 - 1.  Each partial product
+// C(n - k + i, i) is an integer below 2^64 before the next step, so the
+// step's product stays below 2^128.
+bool binom(uint64_t n, uint64_t k, uint64_t* out) {
   u128 r = 1;
   for (uint64_t i = 1; i <= k; ++i) {
     r = r * (n - k + i) / i;
-    if (r > (u128)UINT64_MAX) return UINT64_MAX;
+    if (r > (u128)UINT64_MAX) return false;
   }
-  return (uint64_t)r;
+  *out = (uint64_t)r;
+  return true;
 }
 
 }  // namespace
@@ -67,6 +71,7 @@ extern "C" int tk_grid_count(int64_t P, int N, uint64_t* count) {
   clear_error();
   if (!count) return fail(TK_EINVAL, "count is null");
   if (P < 1 || N < 1) return fail(TK_EINVAL, "P >= 1 and N >= 1 required");
+  // r stays below 2^64 after every factor, so each product fits in 128 bits
   u128 r = 1;
   int64_t x = P;
   for (int64_t p = 2; p * p <= x; ++p) {
@@ -75,7 +80,13 @@ extern "C" int tk_grid_count(int64_t P, int N, uint64_t* count) {
       x /= p;
       ++e;
     }
-    if (e) r *= binom((uint64_t)(e + N - 1), (uint64_t)(N - 1));
+    if (e) {
+      uint64_t c = 0;
+      if (!binom((uint64_t)e + (uint64_t)N - 1, (uint64_t)N - 1, &c))
+        return fail(TK_EINVAL, "count overflows 64 bits");
+      r *= c;
+      if (r > (u128)UINT64_MAX) return fail(TK_EINVAL, "count overflows 64 bits");
+    }
   }
   if (x > 1) r *= (uint64_t)N;  // one prime to the first power: C(N, N - 1)
   if (r > (u128)UINT64_MAX) return fail(TK_EINVAL, "count overflows 64 bits");
