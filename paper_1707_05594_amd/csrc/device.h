@@ -84,6 +84,67 @@ __device__ __forceinline__ f4 load4_f32(const _Float16* p) {
   return r;
 }
 
+// A pointer read from device memory (a descriptor table) is generic to the
+// compiler, which then emits flat loads and stores: those count against the
+// LDS wait counter too, so every wait for an LDS read also waits for the
+// memory loads in flight.  All device buffers live in the global address
+// space; rebuilding the pointer there from its integer value lets the
+// compiler use global instructions (a plain cast there and back is folded
+// away before the address space is inferred).
+template <typename T>
+__device__ __forceinline__ T* global_ptr(T* p) {
+  typedef __attribute__((address_space(1))) T GT;
+  return (T*)(GT*)(uintptr_t)p;
+}
+
+// Four consecutive elements as loaded (FP32: four floats; 2-byte types: two
+// 32-bit words), and their conversion to FP32: lets a pipeline hold loaded
+// rows in their storage width until use.
+template <typename T>
+struct Raw4 {
+  typedef u2v type;
+};
+template <>
+struct Raw4<float> {
+  typedef f4 type;
+};
+template <bool NT = false, typename T>
+__device__ __forceinline__ typename Raw4<T>::type load4_raw(const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    return load4_f32<NT>(p);
+  } else {
+    static_assert(sizeof(T) == 2, "4- or 2-byte element types only");
+    if constexpr (NT)
+      return __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+    else
+      return *reinterpret_cast<const u2v*>(p);
+  }
+}
+template <typename T>
+__device__ __forceinline__ f4 raw4_to_f32(typename Raw4<T>::type v);
+template <>
+__device__ __forceinline__ f4 raw4_to_f32<float>(f4 v) {
+  return v;
+}
+template <>
+__device__ __forceinline__ f4 raw4_to_f32<uint16_t>(u2v v) {
+  f4 r;
+  r[0] = __uint_as_float(v[0] << 16);
+  r[1] = __uint_as_float(v[0] & 0xFFFF0000u);
+  r[2] = __uint_as_float(v[1] << 16);
+  r[3] = __uint_as_float(v[1] & 0xFFFF0000u);
+  return r;
+}
+template <>
+__device__ __forceinline__ f4 raw4_to_f32<_Float16>(u2v v) {
+  f4 r;
+  r[0] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[0] & 0xFFFFu));
+  r[1] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[0] >> 16));
+  r[2] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[1] & 0xFFFFu));
+  r[3] = (float)__builtin_bit_cast(_Float16, (uint16_t)(v[1] >> 16));
+  return r;
+}
+
 // Wave-level sum (64 lanes) of a double, result valid in every lane.
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

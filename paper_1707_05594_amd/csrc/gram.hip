@@ -194,8 +194,8 @@ __global__ __launch_bounds__(256, sizeof(TIn) == 8 ? 2 : 4) void gram_grouped_pa
   __shared__ double Xj[kGC][kGP];
   const int4 w = items[blockIdx.x];
   const GramDesc d = mats[w.x];
-  gram_partial_body<TIn>((const TIn*)d.Y, d.L, d.B, d.C, d.cchunk, d.T, d.npairs, d.part, w.y,
-                         w.z, Xi, Xj);
+  gram_partial_body<TIn>(global_ptr((const TIn*)d.Y), d.L, d.B, d.C, d.cchunk, d.T, d.npairs,
+                         global_ptr(d.part), w.y, w.z, Xi, Xj);
 }
 
 // Sum over chunks of element (i, j) of an L x L Gram: kRG thread groups of
@@ -282,7 +282,8 @@ __global__ __launch_bounds__(256) void gram_grouped_reduce(const GramDesc* __res
   }
   const int ti = ii / kGT, tj = jj / kGT;
   const int p = ti * d.T - ti * (ti - 1) / 2 + (tj - ti);
-  const double* src = d.part + (int64_t)p * (kGT * kGT) + (ii - ti * kGT) * kGT + (jj - tj * kGT);
+  const double* src =
+      global_ptr(d.part) + (int64_t)p * (kGT * kGT) + (ii - ti * kGT) * kGT + (jj - tj * kGT);
   const int64_t stride = (int64_t)d.npairs * (kGT * kGT);
   double t = 0.0;
   if (d.nchunks <= kRG) {
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(256) void gram_grouped_reduce(const GramDesc* __res
       t += s;
     }
   }
-  d.S[rel] = t;
+  global_ptr(d.S)[rel] = t;
 }
 
 namespace {

@@ -60,29 +60,64 @@ __device__ __forceinline__ void stage_factor(float* FT, const float* __restrict_
 // the root), so its loads bypass cache retention.
 // MFMA chain of one wide-path lane over rows [l0, l1) of its four columns
 // (input at p, row stride B); acc[g][j][m] is output k = k0 + 4g + m of
-// column j.
+// column j.  Software-pipelined: U rows are in flight from the start, and
+// each row's registers are refilled with the row U further on as soon as the
+// MFMAs that consume them are issued, so U loads stay outstanding while the
+// MFMAs run; the factor values of the next row are read from LDS one row
+// ahead.  Rows wait in registers as loaded (2-byte inputs: two registers per
+// row, converted at use).
 template <int KG, typename TIn, bool NT>
 __device__ __forceinline__ void wide_chain(const TIn* __restrict__ p, int64_t B,
                                            const float* __restrict__ ft, int l0, int l1,
                                            f4 (&acc)[KG][4]) {
+  typedef typename Raw4<TIn>::type R;
   constexpr int U = 8;
   int l = l0;
-  for (; l + U <= l1; l += U) {
-    f4 x[U];
+  if (l + U <= l1) {
+    R x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-      x[u] = load4_f32<NT>(p + (int64_t)(l + u) * B);
-    // keep the batch of loads together ahead of the MFMAs that consume them
-    __builtin_amdgcn_sched_barrier(0);
+    for (int u = 0; u < U; ++u) x[u] = load4_raw<NT>(p + (int64_t)(l + u) * B);
+    float fa[KG];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int g = 0; g < KG; ++g) fa[g] = ft[l * KG + g];
+    // rows l .. l + U - 1 in registers; rows up to l + 2U - 1 < l1 exist
+    for (; l + 2 * U <= l1; l += U) {
 #pragma unroll
-      for (int g = 0; g < KG; ++g) {
-        const float fa = ft[(l + u) * KG + g];
+      for (int u = 0; u < U; ++u) {
+        float fn[KG];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+        for (int g = 0; g < KG; ++g) fn[g] = ft[(l + u + 1) * KG + g];
+        const f4 xv = raw4_to_f32<TIn>(x[u]);
+#pragma unroll
+        for (int g = 0; g < KG; ++g)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa[g], xv[j], acc[g][j]);
+        x[u] = load4_raw<NT>(p + (int64_t)(l + U + u) * B);
+#pragma unroll
+        for (int g = 0; g < KG; ++g) fa[g] = fn[g];
+        // one row per group: the refill stays behind its row's MFMAs
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
+    // the last batch in registers: nothing further to fetch
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float fn[KG];
+      if (u + 1 < U) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) fn[g] = ft[(l + u + 1) * KG + g];
+      }
+      const f4 xv = raw4_to_f32<TIn>(x[u]);
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa[g], xv[j], acc[g][j]);
+      if (u + 1 < U) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) fa[g] = fn[g];
+      }
+    }
+    l += U;
   }
   for (; l < l1; ++l) {
     const f4 x = load4_f32<NT>(p + (int64_t)l * B);
@@ -215,8 +250,13 @@ __global__ __launch_bounds__(256) void ttm_wide_splitl_f32(const TIn* __restrict
     wide_splitl_body<KG, TIn, NT>(in, F, out, C, L, B, Kt, blockIdx.x, blockIdx.y * 4 * KG, smem);
 }
 
+// Four waves per SIMD where the accumulators leave room (KG <= 4: the
+// pipelined chain holds 16 KG accumulators, 32 input registers and the
+// factor values of two rows).
+constexpr int wide_min_waves(int KG) { return KG <= 4 ? 4 : 1; }
+
 template <int KG, typename TIn, bool NT>
-__global__ __launch_bounds__(256) void ttm_wide_f32(const TIn* __restrict__ in,
+__global__ __launch_bounds__(256, wide_min_waves(KG)) void ttm_wide_f32(const TIn* __restrict__ in,
                                                     const float* __restrict__ F,
                                                     float* __restrict__ out, int64_t C, int L,
                                                     int64_t B, int Kt) {
@@ -1093,7 +1133,10 @@ __global__ __launch_bounds__(256, 3) void ttm_grouped(const TtmNodeDesc* __restr
     __syncthreads();  // every thread has read s_item and finished the previous item
     if (it >= n_items) break;
     const int2 w = items[it];
-    const TtmNodeDesc d = nodes[w.x];
+    TtmNodeDesc d = nodes[w.x];
+    d.in = global_ptr(d.in);
+    d.F = global_ptr(d.F);
+    d.out = global_ptr(d.out);
     // streaming loads only where no 128-byte line is shared between runs
     const bool nt = NT && d.lines;
     if (d.path == kGroupedWide) {
@@ -1148,7 +1191,8 @@ __global__ __launch_bounds__(256) void ttm_grouped_rows(const TtmNodeDesc* __res
     if (it >= n_items) break;
     const int2 w = items[it];
     const TtmNodeDesc d = nodes[w.x];
-    rows_body<4, TIn, NT, false>((const TIn*)d.in, d.F, d.out, d.A, d.L, d.K, w.y, 0, smem);
+    rows_body<4, TIn, NT, false>(global_ptr((const TIn*)d.in), global_ptr(d.F),
+                                 global_ptr(d.out), d.A, d.L, d.K, w.y, 0, smem);
   }
 }
 
