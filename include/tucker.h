@@ -342,6 +342,11 @@ typedef struct tk_mlp tk_mlp;
 int64_t tk_mlp_param_count(int in_dim, int hidden);
 int tk_mlp_create(int in_dim, int hidden, const float* params_host, tk_mlp** out);
 int tk_mlp_set_norm(tk_mlp* m, const float* mu, const float* sigma);
+/* Standardisation from training data: mu = per-feature mean and sigma =
+ * per-feature population standard deviation of the n x in_dim rows of
+ * X_host (row-major), in FP64; a feature whose deviation is at most 1e-6
+ * keeps sigma = 1.  TK_EINVAL for n < 1 or non-finite features. */
+int tk_mlp_fit_norm(tk_mlp* m, const float* X_host, int n);
 int tk_mlp_get_params(const tk_mlp* m, float* host);
 int tk_mlp_set_params(tk_mlp* m, const float* host); /* also resets Adam's moments */
 int tk_mlp_forward(tk_mlp* m, const float* X_host, int n, float* y_host);
@@ -350,6 +355,32 @@ int tk_mlp_loss_grad(tk_mlp* m, const float* X_host, const float* y_host, int n,
 int tk_mlp_train(tk_mlp* m, const float* X_host, const float* y_host, int n, int steps,
                  float lr, float* loss_host /* steps values or NULL */);
 void tk_mlp_free(tk_mlp* m);
+
+/* The TTM view of an internal node as the engine runs it: In viewed as
+ * [A, L, B] row-major (Sec. 2.1), K outputs, its input and output storage
+ * types (TK_F64/F32/BF16/F16) and compute mode (TK_C_*) under the precision
+ * rules of hooi_init for the given storage type and compute mode. */
+typedef struct {
+  int32_t node;      /* index in tk_plan_nodes order                */
+  int32_t in_dtype;  /* storage type of In                          */
+  int32_t out_dtype; /* storage type of the node's output           */
+  int32_t compute;   /* TK_C_* the node's TTM runs at               */
+  int64_t A, L, B, K;
+} tk_node_view;
+/* Views of the internal nodes of tree `rank` (parents first), as
+ * tk_plan_learned weighs them and hooi_init runs them (the plan's tiles for
+ * that rank, when set, enter the storage-type rules).  out NULL: only *n.
+ * Errors: TK_EINVAL (null plan or n, bad rank, dtype or compute, cap below
+ * the internal node count). */
+int tk_plan_node_views(const tk_plan* plan, int rank, int tdtype, int compute,
+                       tk_node_view* out, int cap, int* n);
+/* The two root children of tree `rank` when the root has exactly two
+ * internal children: view7 = (A, Lp, M, Lq, B, Kp, Kq) with T viewed as
+ * [A, Lp, M, Lq, B] for their modes p < q; *fusable = 1 when a pair kernel
+ * takes them for this storage type and compute mode (tk_ttm_pair).  Other
+ * roots: view7 zeroed and *fusable = 0.  Errors: TK_EINVAL. */
+int tk_plan_root_pair(const tk_plan* plan, int rank, int tdtype, int compute, int64_t* view7,
+                      int* fusable);
 
 /* Choose among the trees a TK_TREE_DP plan holds (topk > 1) and each
  * internal node's kernel by the model's predicted time (sum over internal

@@ -43,6 +43,13 @@ class TkNode(ctypes.Structure):
                 ("pad_", ctypes.c_uint32)]
 
 
+class TkNodeView(ctypes.Structure):
+    _fields_ = [("node", ctypes.c_int32), ("in_dtype", ctypes.c_int32),
+                ("out_dtype", ctypes.c_int32), ("compute", ctypes.c_int32),
+                ("A", ctypes.c_int64), ("L", ctypes.c_int64), ("B", ctypes.c_int64),
+                ("K", ctypes.c_int64)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -107,6 +114,7 @@ _SIGS = {
     "tk_mlp_param_count": ([ctypes.c_int, ctypes.c_int], ctypes.c_int64),
     "tk_mlp_create": ([ctypes.c_int, ctypes.c_int, _fp, ctypes.POINTER(_vp)], ctypes.c_int),
     "tk_mlp_set_norm": ([_vp, _fp, _fp], ctypes.c_int),
+    "tk_mlp_fit_norm": ([_vp, _fp, ctypes.c_int], ctypes.c_int),
     "tk_mlp_get_params": ([_vp, _fp], ctypes.c_int),
     "tk_mlp_set_params": ([_vp, _fp], ctypes.c_int),
     "tk_mlp_forward": ([_vp, _fp, ctypes.c_int, _fp], ctypes.c_int),
@@ -116,6 +124,10 @@ _SIGS = {
     "tk_mlp_free": ([_vp], None),
     "tk_plan_learned": ([_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, _ip, _dp],
                         ctypes.c_int),
+    "tk_plan_node_views": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int,
+                            _ip], ctypes.c_int),
+    "tk_plan_root_pair": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, _ip],
+                          ctypes.c_int),
     "hooi_batch_init": ([ctypes.c_int, _ip, _i64p, _i64p, ctypes.c_int, ctypes.POINTER(_vp),
                          ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
     "hooi_batch_iterate": ([_vp, ctypes.c_int, _dp], ctypes.c_int),
@@ -240,6 +252,33 @@ class Plan:
                                    ctypes.byref(vol)))
         return (int(vol.value), tuple(root),
                 [tuple(per[u * N:(u + 1) * N]) for u in range(n)])
+
+    def node_views(self, rank=0, tdtype="f32", compute="fp32"):
+        """The internal nodes' TTM views as the engine runs them: dicts of
+        node, A, L, B, K, in_dtype, out_dtype, compute (names)."""
+        n = ctypes.c_int()
+        _check(lib().tk_plan_node_views(self._h, rank, DTYPES[tdtype], COMPUTE[compute], None,
+                                        0, ctypes.byref(n)))
+        arr = (TkNodeView * n.value)()
+        _check(lib().tk_plan_node_views(self._h, rank, DTYPES[tdtype], COMPUTE[compute], arr,
+                                        n.value, ctypes.byref(n)))
+        dn = {v: k for k, v in DTYPES.items()}
+        cn = {v: k for k, v in COMPUTE.items()}
+        return [dict(node=x.node, A=int(x.A), L=int(x.L), B=int(x.B), K=int(x.K),
+                     in_dtype=dn[x.in_dtype], out_dtype=dn[x.out_dtype],
+                     compute=cn[x.compute]) for x in arr]
+
+    def root_pair(self, rank=0, tdtype="f32", compute="fp32"):
+        """(A, Lp, M, Lq, B, Kp, Kq) of the two root children, and whether a
+        pair kernel takes them; (None, False) unless the root has exactly two
+        internal children."""
+        v = (ctypes.c_int64 * 7)()
+        f = ctypes.c_int()
+        _check(lib().tk_plan_root_pair(self._h, rank, DTYPES[tdtype], COMPUTE[compute], v,
+                                       ctypes.byref(f)))
+        if v[0] == 0:
+            return None, False
+        return tuple(int(x) for x in v), bool(f.value)
 
     def learned(self, model, tdtype="f32", compute="fp32", margin=0.02):
         """Select a held tree and per-node kernels by the cost model; returns
@@ -557,6 +596,11 @@ class MLP:
     def set_norm(self, mu, sigma):
         mu, sigma = _f32(mu), _f32(sigma)
         _check(lib().tk_mlp_set_norm(self._h, mu.ctypes.data_as(_fp), sigma.ctypes.data_as(_fp)))
+
+    def fit_norm(self, X):
+        """Standardise features by the per-feature mean and deviation of X."""
+        X = _f32(X)
+        _check(lib().tk_mlp_fit_norm(self._h, X.ctypes.data_as(_fp), X.shape[0]))
 
     def params(self):
         import numpy as np

@@ -22,18 +22,11 @@ from . import (COMPUTE, DTYPES, MLP, TK_FEATURES, TK_TILE_COUNT, TuckerError, ml
 
 
 def node_views(L, K, plan, rank, tdtype="f32", compute="fp32"):
-    """(A, L, B, K, in_dtype) of every internal node of tree `rank`."""
-    out = []
-    for nd in plan.nodes(rank):
-        if nd["is_leaf"]:
-            continue
-        n, pre = nd["mode"], nd["pre_mask"]
-        dims = [K[j] if (pre >> j) & 1 else L[j] for j in range(len(L))]
-        A = int(np.prod(dims[:n], dtype=np.int64))
-        B = int(np.prod(dims[n + 1:], dtype=np.int64))
-        in_dt = tdtype if nd["parent"] < 0 else ("f64" if compute == "fp64" else "f32")
-        out.append((A, dims[n], B, K[n], in_dt))
-    return out
+    """(A, L, B, K, in_dtype, compute) of every internal node of tree `rank`,
+    as the engine runs it (from the library: per-node storage types and
+    compute modes of hooi_init)."""
+    return [(v["A"], v["L"], v["B"], v["K"], v["in_dtype"], v["compute"])
+            for v in plan.node_views(rank, tdtype, compute)]
 
 
 def candidate_views(L, K, topk=8, tdtype="f32", compute="fp32"):
@@ -48,14 +41,7 @@ def candidate_views(L, K, topk=8, tdtype="f32", compute="fp32"):
 
 def root_pair_view(L, K, plan, rank):
     """(A, Lp, M, Lq, B, Kp, Kq) of tree `rank`'s two root children, or None."""
-    roots = [nd for nd in plan.nodes(rank) if nd["parent"] < 0]
-    if len(roots) != 2 or any(nd["is_leaf"] for nd in roots):
-        return None
-    p, q = sorted(nd["mode"] for nd in roots)
-    A = int(np.prod(L[:p], dtype=np.int64))
-    M = int(np.prod(L[p + 1:q], dtype=np.int64))
-    B = int(np.prod(L[q + 1:], dtype=np.int64))
-    return (A, L[p], M, L[q], B, K[p], K[q])
+    return plan.root_pair(rank)[0]
 
 
 def candidate_pairs(L, K, topk=8, trailing=True):
@@ -95,12 +81,13 @@ def random_pair_views(count, seed, min_elems=int(2e7), max_elems=int(3e9)):
     return out
 
 
-def pair_node_views(pairs, tdtype="f32"):
-    """The two separate root TTMs of each pair view: (A, L, B, K, dtype)."""
+def pair_node_views(pairs, tdtype="f32", compute="fp32"):
+    """The two separate root TTMs of each pair view: T as [A, Lp, M Lq B]
+    and as [A Lp M, Lq, B]."""
     out = []
     for A, Lp, M, Lq, B, Kp, Kq in pairs:
-        out.append((A, Lp, M * Lq * B, Kp, tdtype))
-        out.append((A * Lp * M, Lq, B, Kq, tdtype))
+        out.append((A, Lp, M * Lq * B, Kp, tdtype, compute))
+        out.append((A * Lp * M, Lq, B, Kq, tdtype, compute))
     return out
 
 
@@ -150,27 +137,30 @@ def random_shapes(count, seed, max_elems=int(1.6e9)):
     return shapes
 
 
-def measure(views, compute="fp32", reps=5, tiles=range(TK_TILE_COUNT), device="cuda:0"):
-    """Time every (view, tile); returns features X (n x TK_FEATURES), log-ms y."""
+def measure(views, reps=5, tiles=range(TK_TILE_COUNT), device="cuda:0"):
+    """Time every (view, tile) for views (A, L, B, K, in_dtype, compute) at
+    their own compute mode (FP32 or reduced; FP64 views are skipped: the
+    tree kernels differ there only by shape); returns features X
+    (n x TK_FEATURES), log-ms y and rows."""
     import torch
     dev = torch.device(device)
-    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}
-    cap_in = max(A * L * B for A, L, B, _, _ in views)
-    cap_out = max(A * K * B for A, _, B, K, _ in views)
-    cap_f = max(L * K for _, L, _, K, _ in views)
-    out_dt = torch.float64 if compute == "fp64" else torch.float32
+    views = [v for v in views if v[5] != "fp64"]
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+    cap_in = max(A * L * B for A, L, B, _, _, _ in views)
+    cap_out = max(A * K * B for A, _, B, K, _, _ in views)
+    cap_f = max(L * K for _, L, _, K, _, _ in views)
     bufs = {}
     for dt in sorted({v[4] for v in views}):
         bufs[dt] = torch.full((cap_in,), 0.5, dtype=tdt[dt], device=dev)
-    F = torch.full((cap_f,), 0.25, dtype=out_dt, device=dev)
-    out = torch.empty((cap_out,), dtype=out_dt, device=dev)
+    F = torch.full((cap_f,), 0.25, dtype=torch.float32, device=dev)
+    out = torch.empty((cap_out,), dtype=torch.float32, device=dev)
     X, y, rows = [], [], []
-    for (A, L, B, K, dt) in views:
+    for (A, L, B, K, dt, comp) in views:
         for t in tiles:
-            ms = time_ttm(bufs[dt], A, L, B, F, K, out, compute=compute, tile=t, reps=reps)
-            X.append(ttm_features(A, L, B, K, dt, compute, t))
+            ms = time_ttm(bufs[dt], A, L, B, F, K, out, compute=comp, tile=t, reps=reps)
+            X.append(ttm_features(A, L, B, K, dt, comp, t))
             y.append(math.log(max(ms, 1e-4)))
-            rows.append((A, L, B, K, dt, t, ms))
+            rows.append((A, L, B, K, dt, comp, t, ms))
     del bufs, F, out
     return np.array(X, dtype=np.float32), np.array(y, dtype=np.float32), rows
 
@@ -209,10 +199,7 @@ def train(X, y, hidden=32, steps=3000, lr=3e-3, seed=0):
     """A trained MLP (standardised features); returns (model, per-step losses)."""
     X = np.asarray(X, dtype=np.float32)
     model = MLP(TK_FEATURES, hidden, init_params(TK_FEATURES, hidden, seed))
-    mu = X.mean(axis=0)
-    sigma = X.std(axis=0)
-    sigma = np.where(sigma > 1e-6, sigma, 1.0).astype(np.float32)
-    model.set_norm(mu, sigma)
+    model.fit_norm(X)
     # the output bias starts at the mean target, so training starts near the data
     p = model.params()
     p[-1] = float(np.mean(y))

@@ -222,6 +222,76 @@ extern "C" int tk_plan_get_tiles(const tk_plan* plan, int rank, int* tiles, int 
   return TK_OK;
 }
 
+extern "C" int tk_plan_node_views(const tk_plan* plan, int rank, int tdtype, int compute,
+                                  tk_node_view* out, int cap, int* n) {
+  clear_error();
+  if (!plan || !n) return fail(TK_EINVAL, "null pointer");
+  if (rank < 0 || rank >= (int)plan->trees.size()) return fail(TK_EINVAL, "rank %d out of range", rank);
+  if (tdtype < TK_F64 || tdtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
+    return fail(TK_EINVAL, "unknown compute mode %d", compute);
+  const Shape& s = plan->shape;
+  const auto& nodes = plan->trees[rank].nodes;
+  int count = 0;
+  for (const tk_node& nd : nodes) count += nd.is_leaf ? 0 : 1;
+  *n = count;
+  if (!out) return TK_OK;
+  if (cap < count) return fail(TK_EINVAL, "cap %d < %d internal nodes", cap, count);
+  const bool set = rank < (int)plan->tiles.size() && !plan->tiles[rank].empty();
+  const std::vector<int> tiles = set ? plan->tiles[rank] : std::vector<int>();
+  int fold_leaf = 0;
+  std::vector<int> node_compute, out_dt;
+  tree_precisions(s, nodes, tdtype, compute, tiles, reinterpret_cast<const void*>((uintptr_t)256),
+                  &fold_leaf, &node_compute, &out_dt);
+  int i = 0;
+  for (int u = 0; u < (int)nodes.size(); ++u) {
+    if (nodes[u].is_leaf) continue;
+    tk_node_view& v = out[i++];
+    v.node = u;
+    v.in_dtype = nodes[u].parent < 0 ? tdtype : out_dt[nodes[u].parent];
+    v.compute = node_compute[u];
+    v.out_dtype = out_dt[u];
+    view(s, nodes[u].pre_mask, nodes[u].mode, &v.A, &v.L, &v.B);
+    v.K = s.K[nodes[u].mode];
+  }
+  return TK_OK;
+}
+
+extern "C" int tk_plan_root_pair(const tk_plan* plan, int rank, int tdtype, int compute,
+                                 int64_t* view7, int* fusable) {
+  clear_error();
+  if (!plan || !view7 || !fusable) return fail(TK_EINVAL, "null pointer");
+  if (rank < 0 || rank >= (int)plan->trees.size()) return fail(TK_EINVAL, "rank %d out of range", rank);
+  if (tdtype < TK_F64 || tdtype > TK_F16) return fail(TK_EINVAL, "unknown dtype %d", tdtype);
+  if (compute < TK_C_FP64 || compute > TK_C_BF16X3)
+    return fail(TK_EINVAL, "unknown compute mode %d", compute);
+  const Shape& s = plan->shape;
+  const auto& nodes = plan->trees[rank].nodes;
+  std::vector<int> roots;
+  for (size_t u = 0; u < nodes.size(); ++u)
+    if (nodes[u].parent < 0) roots.push_back((int)u);
+  *fusable = 0;
+  if (roots.size() != 2 || nodes[roots[0]].is_leaf || nodes[roots[1]].is_leaf) {
+    for (int i = 0; i < 7; ++i) view7[i] = 0;
+    return TK_OK;
+  }
+  const int p = std::min(nodes[roots[0]].mode, nodes[roots[1]].mode);
+  const int q = std::max(nodes[roots[0]].mode, nodes[roots[1]].mode);
+  int64_t Ap, Lp, Bp, Aq, Lq, Bq;
+  view(s, 0, p, &Ap, &Lp, &Bp);
+  view(s, 0, q, &Aq, &Lq, &Bq);
+  view7[0] = Ap;
+  view7[1] = Lp;
+  view7[2] = Aq / (Ap * Lp);
+  view7[3] = Lq;
+  view7[4] = Bq;
+  view7[5] = s.K[p];
+  view7[6] = s.K[q];
+  int up, uq;
+  *fusable = fusable_pair(s, nodes, tdtype, compute, &up, &uq) ? 1 : 0;
+  return TK_OK;
+}
+
 extern "C" int tk_plan_learned(tk_plan* plan, tk_mlp* model, int tdtype, int compute,
                                double margin, int* chosen, double* predicted_ms) {
   clear_error();

@@ -286,6 +286,29 @@ extern "C" int tk_mlp_set_norm(tk_mlp* m, const float* mu, const float* sigma) {
   return TK_OK;
 }
 
+extern "C" int tk_mlp_fit_norm(tk_mlp* m, const float* X_host, int n) {
+  clear_error();
+  if (!m || !X_host) return fail(TK_EINVAL, "null pointer");
+  if (n < 1) return fail(TK_EINVAL, "n=%d < 1", n);
+  std::vector<float> mu(m->D), sigma(m->D);
+  for (int i = 0; i < m->D; ++i) {
+    double sum = 0.0;
+    for (int r = 0; r < n; ++r) sum += (double)X_host[(size_t)r * m->D + i];
+    const double mean = sum / n;
+    double ss = 0.0;
+    for (int r = 0; r < n; ++r) {
+      const double d = (double)X_host[(size_t)r * m->D + i] - mean;
+      ss += d * d;
+    }
+    const double sd = std::sqrt(ss / n);
+    if (!std::isfinite(mean) || !std::isfinite(sd))
+      return fail(TK_EINVAL, "feature %d is not finite", i);
+    mu[i] = (float)mean;
+    sigma[i] = sd > 1e-6 ? (float)sd : 1.f;  // constant feature: leave it unscaled
+  }
+  return tk_mlp_set_norm(m, mu.data(), sigma.data());
+}
+
 extern "C" int tk_mlp_get_params(const tk_mlp* m, float* host) {
   clear_error();
   if (!m || !host) return fail(TK_EINVAL, "null pointer");

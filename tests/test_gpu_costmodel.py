@@ -55,6 +55,27 @@ def test_mlp_forward_and_gradient_match_oracle():
     assert rel_err(g, g_o) < 1e-4
 
 
+def test_mlp_fit_norm_standardises_like_the_definition():
+    """tk_mlp_fit_norm: the oracle's forward with the per-feature mean and
+    population deviation of X (a constant feature keeps sigma = 1)."""
+    torch_dev()
+    X, _ = _data(300, 4)
+    X[:, 5] = 7.0  # constant feature
+    p = cm.init_params(D, H, 5)
+    m = tk.MLP(D, H, p)
+    m.fit_norm(X)
+    X64 = X.astype(np.float64)
+    mu = X64.mean(axis=0)
+    sg = X64.std(axis=0)
+    sg[5] = 1.0
+    # the library rounds mu and sigma to FP32 as set_norm stores them
+    want, _ = M.forward(p.astype(np.float64), X, mu.astype(np.float32).astype(np.float64),
+                        sg.astype(np.float32).astype(np.float64), D, H)
+    assert rel_err(m.forward(X), want) < 1e-5
+    with pytest.raises(tk.TuckerError):
+        m.fit_norm(X[:0])
+
+
 def test_mlp_adam_steps_match_oracle():
     torch_dev()
     X, y = _data(257, 2)

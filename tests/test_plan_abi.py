@@ -183,3 +183,68 @@ def test_hooi_init_validates_before_touching_the_device():
                                      None, None, ctypes.byref(h)) == tk.TK_EUNSUPPORTED
     assert lib.hooi_init(3, Lc, Kc, tk.TK_F16 + 1, ctypes.c_void_p(16), None, tk.TK_C_FP32,
                          None, None, ctypes.byref(h)) == tk.TK_EINVAL
+
+
+def _view_from_definition(L, K, nd):
+    """[A, L_n, B] of a node's input from its premultiplied modes (Sec. 2.1)."""
+    dims = [K[j] if (nd["pre_mask"] >> j) & 1 else L[j] for j in range(len(L))]
+    n = nd["mode"]
+    return int(np.prod(dims[:n], dtype=np.int64)), L[n], int(np.prod(dims[n + 1:], dtype=np.int64))
+
+
+@pytest.mark.parametrize("L,K", [((64, 48, 40, 32, 24, 16), (8, 8, 6, 6, 4, 4)),
+                                 ((200, 200, 200, 200), (20, 20, 20, 20)),
+                                 ((30, 7, 9, 5), (3, 2, 4, 2)),
+                                 ((80, 80, 80, 80, 80), (10, 10, 10, 10, 10))])
+def test_node_views_and_root_pair_follow_the_definition(L, K):
+    """tk_plan_node_views against the node's view computed here from its
+    premultiplied modes, for every held tree; storage types and compute modes
+    by the engine's rules: FP32 storage and compute keep FP32 everywhere; in
+    the BF16 modes the root reads the stored T and the path to the leaf of the
+    smallest Y_n (the core's fold) runs at FP32; tk_plan_root_pair against
+    the root children's modes."""
+    plan = tk.ttm_tree_plan(L, K, "dp", topk=4)
+    N = len(L)
+    # the leaf whose Y (all other modes multiplied) is smallest; ties: lowest mode
+    ysize = [int(np.prod([K[m] for m in range(N) if m != n])) * L[n] for n in range(N)]
+    fold = int(np.argmin(ysize))
+    for r in range(plan.count):
+        nodes = plan.nodes(r)
+        internal = [u for u, nd in enumerate(nodes) if not nd["is_leaf"]]
+        v32 = plan.node_views(r, "f32", "fp32")
+        assert [v["node"] for v in v32] == internal
+        for v in v32:
+            assert (v["A"], v["L"], v["B"]) == _view_from_definition(L, K, nodes[v["node"]])
+            assert v["K"] == K[nodes[v["node"]]["mode"]]
+            assert (v["in_dtype"], v["out_dtype"], v["compute"]) == ("f32", "f32", "fp32")
+        on_fold = set()
+        for u, nd in enumerate(nodes):
+            if nd["is_leaf"] and nd["mode"] == fold:
+                w = nd["parent"]
+                while w >= 0:
+                    on_fold.add(w)
+                    w = nodes[w]["parent"]
+        for comp in ("bf16", "bf16x3"):
+            for v in plan.node_views(r, "bf16", comp):
+                nd = nodes[v["node"]]
+                assert v["compute"] == ("fp32" if v["node"] in on_fold else comp)
+                if nd["parent"] < 0:
+                    assert v["in_dtype"] == "bf16"
+                else:
+                    assert v["in_dtype"] in ("f32", "bf16")
+        for v in plan.node_views(r, "f16", "fp32"):
+            assert v["in_dtype"] == ("f16" if nodes[v["node"]]["parent"] < 0 else "f32")
+        roots = [nd for nd in nodes if nd["parent"] < 0]
+        pv, fusable = plan.root_pair(r)
+        if len(roots) == 2 and not any(nd["is_leaf"] for nd in roots):
+            p, q = sorted(nd["mode"] for nd in roots)
+            want = (int(np.prod(L[:p])), L[p], int(np.prod(L[p + 1:q])), L[q],
+                    int(np.prod(L[q + 1:])), K[p], K[q])
+            assert pv == want
+            # the pair kernel: trailing modes (M = B = 1) of an FP32 tensor
+            if fusable:
+                assert want[2] == 1 and want[4] == 1
+        else:
+            assert pv is None and not fusable
+    with pytest.raises(tk.TuckerError):
+        plan.node_views(plan.count, "f32", "fp32")
