@@ -420,8 +420,10 @@ int tk_ttm(int in_dtype, int compute, const void* in, int64_t A, int64_t L, int6
  *   outp[a, kp, m, lq, b] = sum_lp Fp[lp, kp] in[a, lp, m, lq, b]   ([A, Kp, M, Lq, B])
  *   outq[a, lp, m, kq, b] = sum_lq Fq[lq, kq] in[a, lp, m, lq, b]   ([A, Lp, M, Kq, B])
  * Fp: Lp x Kp, Fq: Lq x Kq row-major FP32, device.  compute: TK_C_FP32.
- * Requirements (else TK_EUNSUPPORTED): B % 4 == 0, Lq <= 256, Kp, Kq <= 20,
- * 16-byte aligned pointers, A * M * B / 4 >= 2048.  Asynchronous on `stream`. */
+ * Requirements (else TK_EUNSUPPORTED): 16-byte aligned pointers, Kp, Kq <= 20,
+ * and either the two trailing modes (M = B = 1) with Lq % 4 == 0, Lq <= 256,
+ * Lp * ceil(Kp / 4) <= 2560 (or Lp * Lq <= 2048, Kp, Kq <= 8, A >= 4096), or
+ * B % 4 == 0, Lq <= 256, A * M * B / 4 >= 2048.  Asynchronous on `stream`. */
 int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
                 int64_t Lq, int64_t B, const void* Fp, int64_t Kp, const void* Fq, int64_t Kq,
                 void* outp, void* outq, void* stream);

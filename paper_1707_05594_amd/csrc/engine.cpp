@@ -1249,8 +1249,10 @@ extern "C" int tk_ttm_pair(int in_dtype, int compute, const void* in, int64_t A,
     return fail(TK_EINVAL, "bad sizes");
   if (!ttm_pair_applies(in_dtype, compute, in, A, Lp, M, Lq, B, Kp, Kq, outp, outq))
     return fail(TK_EUNSUPPORTED,
-                "fused pair needs FP32 input and compute, B %% 4 == 0, Lq <= 256, K <= 20, "
-                "16-byte aligned buffers and at least 2048 tiles of four columns");
+                "fused pair needs FP32 input and compute, 16-byte aligned buffers and "
+                "either the two trailing modes (M = B = 1) with Lq %% 4 == 0, Lq <= 256, "
+                "K <= 20, or B %% 4 == 0, Lq <= 256, K <= 20 and at least 2048 tiles of "
+                "four columns");
   TK_HIP(launch_ttm_pair((const float*)in, A, Lp, M, Lq, B, (const float*)Fp, Kp,
                          (const float*)Fq, Kq, (float*)outp, (float*)outq, (hipStream_t)stream));
   return TK_OK;

@@ -28,7 +28,9 @@ bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int6
                       int64_t M, int64_t Lq, int64_t B, int64_t Kp, int64_t Kq,
                       const void* outp, const void* outq);
 // 0: no pair kernel; 1: the general one (lanes over Lq rows, B % 4 == 0);
-// 2: the trailing-modes one (M = B = 1, slabs staged in LDS).
+// 2: the trailing-modes one (M = B = 1, slabs staged in LDS); 3: the
+// trailing-modes one for large slabs (M = B = 1, Lq % 4 == 0, Lq <= 256,
+// ranks <= 20; slabs streamed through LDS in row chunks).
 int ttm_pair_kind(int in_dtype, int compute, const void* in, int64_t A, int64_t Lp, int64_t M,
                   int64_t Lq, int64_t B, int64_t Kp, int64_t Kq, const void* outp,
                   const void* outq);

@@ -309,6 +309,202 @@ __global__ __launch_bounds__(kPairThreads) void ttm_pair_tail_f32(
   }
 }
 
+// ---- the two trailing modes, slabs too large for one block's LDS: T[a] of
+// Lp x Lq elements (Lq % 4 == 0, Lq <= 256), ranks up to 20.  A block owns
+// NA consecutive slabs and streams them through LDS in chunks of R rows
+// (R a multiple of 4, R Lq <= 4096, R <= 16), the 16-byte loads of the next chunk in
+// flight while the current one is used.  LDS rows have 256 columns (zeros
+// past Lq, written once) at the odd pitch 257: column walks and row walks
+// are both free of bank conflicts, and each wave's quarter of a row is a
+// fixed 64 columns.
+// From the same LDS rows both outputs run on v_mfma_f32_4x4x1_16b_f32:
+//   * Outp[a, kp, lq]: lane lq = 64 w + i of wave w accumulates
+//     Fp[lp, 4g + r] x T[a, lp, lq] over every row lp of the slab (the wide
+//     body's pattern, one column per lane, KGP accumulators);
+//   * Outq[a, lp, kq]: the 16 blocks of an MFMA are (rank group g, row quad
+//     q) pairs of the chunk (KGQ groups x R / 4 quads); wave w sums over its
+//     quarter of the columns lq, with the factor entries Fq[lq, 4g + r] it
+//     needs held in registers for the whole block, and the four waves'
+//     partial sums are added in wave order through LDS and stored once per
+//     chunk (deterministic).
+constexpr int kSlabMaxLq = 256;
+constexpr int kSlabPitch = kSlabMaxLq + 1;
+constexpr int kSlabJw = kSlabMaxLq / 4;  // columns per wave in the Outq sums
+constexpr int kSlabChunk = 4096;         // elements of T per chunk
+constexpr int kSlabMaxFp = 2560;         // Lp * KGP: the staged Fp within 40 KB
+
+template <int KGP, int KGQ, bool NT>
+__global__ __launch_bounds__(kPairThreads) void ttm_pair_slab_f32(
+    const float* __restrict__ in, int64_t A, int Lp, int Lq, int R,
+    const float* __restrict__ Fp, int Kp, const float* __restrict__ Fq, int Kq,
+    float* __restrict__ outp, float* __restrict__ outq, int NA) {
+  extern __shared__ float lds[];
+  constexpr int pitch = kSlabPitch;
+  float* S = lds;                   // R x pitch: the current chunk
+  float* FpS = S + R * pitch;       // FT[r][lp][g] = Fp[lp, 4g + r]
+  float* red = FpS + 4 * Lp * KGP;  // [wave][m][lane] partial sums of Outq
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < R * pitch; e += kPairThreads) S[e] = 0.f;  // padding stays zero
+  for (int e = tid; e < 4 * Lp * KGP; e += kPairThreads) {
+    const int g = e % KGP, t = e / KGP, l = t % Lp, r = t / Lp;
+    const int k = 4 * g + r;
+    FpS[e] = k < Kp ? Fp[(int64_t)l * Kp + k] : 0.f;
+  }
+  // Outq: block beta = lane / 4 is (group gq, row quad qq) when beta < KGQ Qn
+  const int Qn = R / 4;
+  const int beta = lane >> 2, kr = lane & 3;
+  const bool qblk = beta < KGQ * Qn;
+  const int gq = qblk ? beta / Qn : 0, qq = qblk ? beta % Qn : 0;
+  const int kq = 4 * gq + kr;
+  const int j0 = wave * kSlabJw;  // this wave's columns j0 .. j0 + 63 (zeros past Lq)
+  float fq[kSlabJw];
+#pragma unroll
+  for (int t = 0; t < kSlabJw; ++t)
+    fq[t] = (j0 + t < Lq && qblk && kq < Kq) ? Fq[(int64_t)(j0 + t) * Kq + kq] : 0.f;
+  // Outp: this lane's column (lanes past Lq read the last column, store nothing)
+  const int jp = wave * 64 + lane;
+  const int jc = min(jp, Lq - 1);
+  const float* ft = FpS + kr * Lp * KGP;
+  const int nchunk = (Lp + R - 1) / R;
+  const int64_t a0 = (int64_t)blockIdx.x * NA;
+  const int na = (int)min<int64_t>(NA, A - a0);
+  const int total = na * nchunk;
+  const float inv_lq = 1.0f / (float)Lq;
+  const int nv_full = R * Lq / 4;  // 16-byte vectors per full chunk (<= 1024)
+  // f4 v = tid + 256 u (u < 4) of chunk s
+  auto fetch = [&](int s, f4 (&pre)[4]) {
+    const int as = s / nchunk, c = s - as * nchunk;
+    const int rc = min(R, Lp - c * R);
+    const float* src = in + ((a0 + as) * Lp + (int64_t)c * R) * Lq;
+    const int nv = rc * Lq / 4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = tid + kPairThreads * u;
+      if (v < nv) {
+        if constexpr (NT)
+          pre[u] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src) + v);
+        else
+          pre[u] = reinterpret_cast<const f4*>(src)[v];
+      } else {
+        pre[u] = f4{0.f, 0.f, 0.f, 0.f};  // rows past Lp in the last chunk
+      }
+    }
+  };
+  f4 pre[4];
+  if (total > 0) fetch(0, pre);
+  f4 accp[KGP];
+#pragma unroll
+  for (int g = 0; g < KGP; ++g) accp[g] = f4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();  // FpS staged
+  for (int s = 0; s < total; ++s) {
+    const int as = s / nchunk, c = s - as * nchunk;
+    const int i0 = c * R, rc = min(R, Lp - i0);
+    // the chunk into LDS (all R rows: zeros past Lp)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = tid + kPairThreads * u;
+      if (v < nv_full) {
+        int col;
+        const int row = small_divmod(4 * v, Lq, inv_lq, &col);
+        float* d = S + row * pitch + col;
+        d[0] = pre[u][0];
+        d[1] = pre[u][1];
+        d[2] = pre[u][2];
+        d[3] = pre[u][3];
+      }
+    }
+    __syncthreads();
+    if (s + 1 < total) fetch(s + 1, pre);
+    // Outp: rows i0 .. i0 + rc - 1 of this slab
+    for (int r = 0; r < rc; ++r) {
+      const float x = S[r * pitch + jc];
+      const float* f = ft + (i0 + r) * KGP;
+#pragma unroll
+      for (int g = 0; g < KGP; ++g) accp[g] = mfma4(f[g], x, accp[g]);
+    }
+    // Outq partial sums over this wave's 64 columns (two chains, even and
+    // odd columns, so consecutive MFMAs do not wait on each other)
+    f4 aq = f4{0.f, 0.f, 0.f, 0.f}, aq1 = f4{0.f, 0.f, 0.f, 0.f};
+    const float* srow = S + (4 * qq + kr) * pitch + j0;
+#pragma unroll
+    for (int t = 0; t < kSlabJw; t += 2) {
+      aq = mfma4(fq[t], srow[t], aq);
+      aq1 = mfma4(fq[t + 1], srow[t + 1], aq1);
+    }
+    aq += aq1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) red[(wave * 4 + m) * 64 + lane] = aq[m];
+    __syncthreads();
+    {
+      // thread (m, l): register m of lane l, summed over the waves in order
+      const int m = tid >> 6, l = tid & 63;
+      const float v = ((red[(0 * 4 + m) * 64 + l] + red[(1 * 4 + m) * 64 + l]) +
+                       red[(2 * 4 + m) * 64 + l]) +
+                      red[(3 * 4 + m) * 64 + l];
+      const int b2 = l >> 2, n = l & 3;
+      if (b2 < KGQ * Qn) {
+        const int row = 4 * (b2 % Qn) + n, k = 4 * (b2 / Qn) + m;
+        if (row < rc && k < Kq) outq[((a0 + as) * Lp + i0 + row) * Kq + k] = v;
+      }
+    }
+    if (c == nchunk - 1) {
+      // the slab is done: Outp[a, kp, lq]
+      if (jp < Lq) {
+        float* o = outp + (a0 + as) * (int64_t)Kp * Lq + jp;
+#pragma unroll
+        for (int g = 0; g < KGP; ++g)
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (4 * g + m < Kp) o[(int64_t)(4 * g + m) * Lq] = accp[g][m];
+      }
+#pragma unroll
+      for (int g = 0; g < KGP; ++g) accp[g] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
+// Rows per chunk: a multiple of 4 with KGQ (R / 4) <= 16 blocks per MFMA,
+// R Lq <= 4096 elements, and R <= 16 (R x 257 floats of LDS beside a staged
+// Fp of up to 40 KB).
+int slab_rows(int Lq, int KGQ) {
+  const int quads = std::min(std::min(16 / KGQ, kSlabChunk / (4 * Lq)), 4);
+  return 4 * std::max(1, quads);
+}
+
+size_t slab_lds(int Lp, int KGP, int R) {
+  return sizeof(float) * ((size_t)R * kSlabPitch + (size_t)4 * Lp * KGP + (size_t)4 * 4 * 64);
+}
+
+bool slab_applies(int64_t A, int64_t Lp, int64_t M, int64_t Lq, int64_t B, int64_t Kp,
+                  int64_t Kq) {
+  if (M != 1 || B != 1 || A < 1 || Lp < 1) return false;
+  if (Lq < 4 || Lq > kSlabMaxLq || Lq % 4 != 0) return false;
+  if (Kp < 1 || Kq < 1 || Kp > 20 || Kq > 20) return false;
+  if (Lp * ((Kp + 3) / 4) > kSlabMaxFp) return false;
+  return A * Lp * Lq < ((int64_t)1 << 40);
+}
+
+template <int KGP, int KGQ>
+hipError_t launch_slab(const float* in, int64_t A, int Lp, int Lq, const float* Fp, int Kp,
+                       const float* Fq, int Kq, float* outp, float* outq, hipStream_t st) {
+  const int R = slab_rows(Lq, KGQ);
+  const size_t lds = slab_lds(Lp, KGP, R);
+  // a few slabs per block where there are many (the staging of the factors
+  // is paid once per block), at least 8192 blocks otherwise
+  const int NA = (int)std::max<int64_t>(1, std::min<int64_t>(4, A / 8192));
+  const unsigned grid = (unsigned)((A + NA - 1) / NA);
+  // streaming loads where every chunk and slab is whole 128-byte lines
+  const bool nt = ((uintptr_t)in % 128 == 0) && ((int64_t)R * Lq * 4) % 128 == 0 &&
+                  ((int64_t)Lp * Lq * 4) % 128 == 0;
+  if (nt)
+    hipLaunchKernelGGL((ttm_pair_slab_f32<KGP, KGQ, true>), dim3(grid), dim3(kPairThreads), lds,
+                       st, in, A, Lp, Lq, R, Fp, Kp, Fq, Kq, outp, outq, NA);
+  else
+    hipLaunchKernelGGL((ttm_pair_slab_f32<KGP, KGQ, false>), dim3(grid), dim3(kPairThreads),
+                       lds, st, in, A, Lp, Lq, R, Fp, Kp, Fq, Kq, outp, outq, NA);
+  return hipGetLastError();
+}
+
 int tail_na(int Lp, int Lq) { return std::max(1, 6144 / (Lp * Lq)); }
 
 size_t tail_lds(int Lp, int Lq, int NA) {
@@ -372,6 +568,7 @@ int ttm_pair_kind(int in_dtype, int compute, const void* in, int64_t A, int64_t 
   if (in_dtype != TK_F32 || compute != TK_C_FP32) return 0;
   if (((uintptr_t)in | (uintptr_t)outp | (uintptr_t)outq) % 16 != 0) return 0;
   if (tail_applies(A, Lp, M, Lq, B, Kp, Kq)) return 2;
+  if (slab_applies(A, Lp, M, Lq, B, Kp, Kq)) return 3;
   return ttm_pair_applies(in_dtype, compute, in, A, Lp, M, Lq, B, Kp, Kq, outp, outq) ? 1 : 0;
 }
 
@@ -379,7 +576,7 @@ bool ttm_pair_applies(int in_dtype, int compute, const void* in, int64_t A, int6
                       int64_t M, int64_t Lq, int64_t B, int64_t Kp, int64_t Kq,
                       const void* outp, const void* outq) {
   if (in_dtype != TK_F32 || compute != TK_C_FP32) return false;
-  if (tail_applies(A, Lp, M, Lq, B, Kp, Kq) &&
+  if ((tail_applies(A, Lp, M, Lq, B, Kp, Kq) || slab_applies(A, Lp, M, Lq, B, Kp, Kq)) &&
       ((uintptr_t)in | (uintptr_t)outp | (uintptr_t)outq) % 16 == 0)
     return true;
   if (B % 4 != 0 || Lq > kPairRows || Lq < 1 || Lp < 1) return false;
@@ -404,6 +601,22 @@ hipError_t launch_ttm_pair(const float* in, int64_t A, int64_t Lp, int64_t M, in
     if (kq == 4)
       return launch_tail<8, 4>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
     return launch_tail<8, 8>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+  }
+  if (slab_applies(A, Lp, M, Lq, B, Kp, Kq)) {
+    const int kgp = (int)((Kp + 3) / 4), kgq = (int)((Kq + 3) / 4);
+#define TK_SLAB_CASE(P, Q)                                                                 \
+  if (kgp == P && kgq == Q)                                                                \
+    return launch_slab<P, Q>(in, A, (int)Lp, (int)Lq, Fp, (int)Kp, Fq, (int)Kq, outp, outq, st);
+#define TK_SLAB_ROW(P) \
+  TK_SLAB_CASE(P, 1) TK_SLAB_CASE(P, 2) TK_SLAB_CASE(P, 3) TK_SLAB_CASE(P, 4) TK_SLAB_CASE(P, 5)
+    TK_SLAB_ROW(1)
+    TK_SLAB_ROW(2)
+    TK_SLAB_ROW(3)
+    TK_SLAB_ROW(4)
+    TK_SLAB_ROW(5)
+#undef TK_SLAB_ROW
+#undef TK_SLAB_CASE
+    return hipErrorInvalidValue;
   }
   const int kgp = (int)((Kp + 3) / 4), kgq = (int)((Kq + 3) / 4);
 #define TK_PAIR_CASE(P, Q)                                                                 \

@@ -478,12 +478,19 @@ def test_ttm_pair_rejects_unsupported():
     assert e.value.code == tk.TK_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("A,Lp,Lq,Kp,Kq", [(4096, 24, 16, 4, 4), (5000, 12, 20, 7, 3),
-                                          (4099, 8, 2, 8, 1), (9000, 1, 4, 1, 4)])
+@pytest.mark.parametrize("A,Lp,Lq,Kp,Kq", [
+    # small slabs staged whole in LDS (the six-mode tensor's root pair)
+    (4096, 24, 16, 4, 4), (5000, 12, 20, 7, 3), (4099, 8, 2, 8, 1), (9000, 1, 4, 1, 4),
+    # large slabs streamed in row chunks: the 200^4 pair (ragged last chunk of
+    # 8 rows), Lq = 256 with a ragged rank group, waves past Lq, a chunk
+    # larger than the slab, two slabs per block with a ragged last block
+    (300, 200, 200, 20, 20), (17, 300, 256, 17, 20), (40, 37, 132, 13, 7), (9, 5, 4, 3, 2),
+    (20001, 12, 40, 5, 9)])
 def test_ttm_pair_trailing_modes(A, Lp, Lq, Kp, Kq):
-    """The pair kernel for the two trailing modes (slabs of Lp x Lq staged in
-    LDS, the six-mode tensor's root pair): both outputs element-wise against
-    the oracle, including a ragged last block of slabs."""
+    """The pair kernels for the two trailing modes (slabs of Lp x Lq staged
+    whole in LDS; or streamed through LDS in row chunks for large slabs and
+    ranks up to 20): both outputs element-wise against the oracle, including
+    ragged last chunks and blocks."""
     torch, dev = torch_dev()
     print(f"ttm pair (trailing) A={A} Lp={Lp} Lq={Lq} Kp={Kp} Kq={Kq}", flush=True)
     g = np.random.default_rng(A + Lp * Lq + Kp + Kq)
