@@ -13,7 +13,7 @@
 //     regridding node takes minimises its own TTM volume plus its subtrees'
 //     optimal volumes; T is laid out under a grid of free choice; ties go to
 //     the first grid in lexicographic order, and to keeping the parent's grid.
-// Nothing here runs on the GPU: this build holds T on one device, so the plan
+// Nothing here runs on the GPU: the engine holds T on one device, so the plan
 // is what a multi-device execution of the same tree would follow.
 #include <algorithm>
 #include <cstring>
