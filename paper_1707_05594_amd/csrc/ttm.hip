@@ -1467,11 +1467,133 @@ hipError_t launch_lk(bool wide, const TIn* in, int64_t A, int L, int64_t B, cons
   return launch_lk_kg<TIn, 12, false>(in, A, L, B, F, K, out, st);
 }
 
+// ---------------------------------------------------------- short-slab path --
+// Nodes whose slabs In[a, :, :] are short (L <= 32, and B = 1 or B < 32 and
+// not a wide-path B; the real tensors' small trailing modes): a wave owns
+// G = 64 / B whole consecutive slabs, so its input (G L B elements) and its
+// output (G K B) are each one contiguous range.  The wave reads its input
+// range with consecutive loads (64 lanes, contiguous bytes per instruction)
+// into its own LDS area, runs the MFMA chain with one column (a, b) per lane
+// (the wide body's pattern), writes the outputs into the same LDS area in
+// their memory order and stores the range with consecutive stores.  The row
+// and tile bodies read 32-column chunks per row and store K scattered
+// elements per row, which leaves most lanes idle on rows of 4 to 16
+// elements.
+constexpr int kShortMaxL = 32;
+constexpr int kShortMaxKG = 8;
+constexpr int kShortLoads = 32;  // 64 L / 64 element loads per lane at most
+
+template <int KG, typename TIn, bool NT>
+__global__ __launch_bounds__(256) void ttm_short_f32(const TIn* __restrict__ in,
+                                                     const float* __restrict__ F,
+                                                     float* __restrict__ out, int64_t A, int L,
+                                                     int B, int Kt, int G, int wbuf) {
+  extern __shared__ float smem[];
+  float* ft_all = smem;  // FT[r][l][g], 4 L KG
+  stage_factor<KG>(ft_all, F, L, Kt, 0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float* buf = smem + 4 * L * KG + wave * wbuf;  // this wave's area
+  const int64_t a0 = ((int64_t)blockIdx.x * 4 + wave) * G;
+  if (a0 >= A) return;  // whole wave idle
+  const int ga = (int)min<int64_t>(G, A - a0);
+  const int n_in = ga * L * B;  // <= 64 L
+  const TIn* src = in + a0 * L * B;
+  float v[kShortLoads];
+#pragma unroll
+  for (int u = 0; u < kShortLoads; ++u) {
+    const int i = u * 64 + lane;
+    if (i < n_in) {
+      if constexpr (NT)
+        v[u] = Elem<TIn>::to_f32(__builtin_nontemporal_load(src + i));
+      else
+        v[u] = Elem<TIn>::to_f32(src[i]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kShortLoads; ++u) {
+    const int i = u * 64 + lane;
+    if (i < n_in) buf[i] = v[u];
+  }
+  wave_lds_fence();
+  // lane = column c = s B + b of slab a0 + s (lanes past G B read column 0
+  // and store nothing)
+  const bool act = lane < ga * B;
+  const int sl = act ? lane / B : 0, b = act ? lane - sl * B : 0;
+  const float* xcol = buf + sl * L * B + b;
+  const float* ft = ft_all + (lane & 3) * L * KG;
+  f4 acc[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) acc[g] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int l = 0; l < L; ++l) {
+    const float x = xcol[l * B];
+#pragma unroll
+    for (int g = 0; g < KG; ++g) acc[g] = mfma4x4x1(ft[l * KG + g], x, acc[g]);
+  }
+  wave_lds_fence();  // every lane's reads are issued before the area is rewritten
+  if (act) {
+#pragma unroll
+    for (int g = 0; g < KG; ++g)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = 4 * g + m;
+        if (k < Kt) buf[(sl * Kt + k) * B + b] = acc[g][m];
+      }
+  }
+  wave_lds_fence();
+  const int n_out = ga * Kt * B;  // <= 64 Kt
+  float* dst = out + a0 * Kt * B;
+  for (int i = lane; i < n_out; i += 64) dst[i] = buf[i];
+}
+
+// Short-slab path: L <= 32, K <= 32, B = 1 or a B the row and tile bodies
+// would take (below 32).
+bool short_applies(int64_t L, int64_t B, int64_t K) {
+  return L >= 1 && L <= kShortMaxL && K >= 1 && K <= 4 * kShortMaxKG && B >= 1 && B < 32;
+}
+
+template <typename TIn, int KG>
+hipError_t launch_short_kg(const TIn* in, int64_t A, int L, int B, const float* F, int K,
+                           float* out, hipStream_t st) {
+  const int G = 64 / B;
+  const int wbuf = G * B * std::max(L, K);
+  const size_t lds = sizeof(float) * ((size_t)4 * L * KG + (size_t)4 * wbuf);
+  const int64_t groups = (A + G - 1) / G;
+  const int64_t blocks = (groups + 3) / 4;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  // streaming loads only where each wave's input range is whole 128-byte lines
+  const bool nt = (uintptr_t)in % 128 == 0 && ((int64_t)G * L * B * sizeof(TIn)) % 128 == 0;
+  if (nt)
+    hipLaunchKernelGGL((ttm_short_f32<KG, TIn, true>), dim3((unsigned)blocks), dim3(256), lds,
+                       st, in, F, out, A, L, B, K, G, wbuf);
+  else
+    hipLaunchKernelGGL((ttm_short_f32<KG, TIn, false>), dim3((unsigned)blocks), dim3(256), lds,
+                       st, in, F, out, A, L, B, K, G, wbuf);
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t launch_short(const TIn* in, int64_t A, int L, int B, const float* F, int K, float* out,
+                        hipStream_t st) {
+  switch ((K + 3) / 4) {
+    case 1: return launch_short_kg<TIn, 1>(in, A, L, B, F, K, out, st);
+    case 2: return launch_short_kg<TIn, 2>(in, A, L, B, F, K, out, st);
+    case 3: return launch_short_kg<TIn, 3>(in, A, L, B, F, K, out, st);
+    case 4: return launch_short_kg<TIn, 4>(in, A, L, B, F, K, out, st);
+    case 5:
+    case 6: return launch_short_kg<TIn, 6>(in, A, L, B, F, K, out, st);
+    default: return launch_short_kg<TIn, 8>(in, A, L, B, F, K, out, st);
+  }
+}
+
 template <typename TIn>
 hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F, int K,
                       float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
   Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, B);
+  if (tile == TK_TILE_AUTO && (path == Path::kRows || path == Path::kTile) &&
+      short_applies(L, B, K))
+    return launch_short<TIn>(in, A, L, (int)B, F, K, out, st);
   // LDS beside the factor slice: the staged tile, or the row tiles when one
   // K-group fits beside them (else 16-byte rows are read directly, and
   // single-element rows take the tile path)

@@ -64,7 +64,18 @@ LK_CASES = [
 ]
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES + LK_CASES)
+# Short slabs (L <= 32; B = 1 or B < 32 off the wide path): a wave owns 64 / B
+# whole slabs, contiguous input and output ranges staged through its LDS
+# area.  Rows of 10, 11, 16 and 4 elements with K close to L (the real
+# tensors' trailing modes), B = 6 and 13 (partial lane use), B = 31 (two
+# slabs per wave), K = 32 (eight groups), ragged last waves and a single slab.
+SHORT_CASES = [
+    (1000, 10, 1, 6), (777, 11, 6, 7), (513, 16, 1, 14), (300, 4, 1, 4),
+    (1001, 32, 3, 32), (65, 5, 31, 3), (129, 7, 13, 5), (1, 3, 1, 2),
+]
+
+
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES + LK_CASES + SHORT_CASES)
 def test_ttm_fp32(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm fp32 A={A} L={L} B={B} K={K}", flush=True)
@@ -80,7 +91,7 @@ def test_ttm_fp32(A, L, B, K):
                        f"ttm fp32 {A}x{L}x{B} K={K}")
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES)
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES + SHORT_CASES)
 def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
     torch, dev = torch_dev()
     print(f"ttm bf16 A={A} L={L} B={B} K={K}", flush=True)
@@ -98,7 +109,7 @@ def test_ttm_bf16_storage_fp32_compute(A, L, B, K):
                        ttm_tol(L, "fp32", bf16_input=True), f"ttm bf16->fp32 {A}x{L}x{B} K={K}")
 
 
-@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES)
+@pytest.mark.parametrize("A,L,B,K", TTM_CASES[:6] + TTM_CASES[-13:] + LK_CASES + SHORT_CASES)
 def test_ttm_f16_storage_fp32_compute(A, L, B, K):
     """IEEE half storage: every value is exact in FP32, so the FP32 kernels
     (converting on load) meet the FP32 bound on the stored values."""
