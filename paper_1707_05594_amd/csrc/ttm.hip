@@ -1483,7 +1483,19 @@ constexpr int kShortMaxL = 32;
 constexpr int kShortMaxKG = 8;
 constexpr int kShortLoads = 32;  // 64 L / 64 element loads per lane at most
 
-template <int KG, typename TIn, bool NT>
+// q = e / d for 0 <= e < 2^22, d >= 1, inv = 1.0f / d (the float quotient is
+// off by at most one and is corrected).
+__device__ __forceinline__ int short_div(int e, int d, float inv) {
+  int q = (int)((float)e * inv);
+  const int r = e - q * d;
+  if (r < 0)
+    --q;
+  else if (r >= d)
+    ++q;
+  return q;
+}
+
+template <int KG, typename TIn, bool NT, bool PAD>
 __global__ __launch_bounds__(256) void ttm_short_f32(const TIn* __restrict__ in,
                                                      const float* __restrict__ F,
                                                      float* __restrict__ out, int64_t A, int L,
@@ -1496,9 +1508,18 @@ __global__ __launch_bounds__(256) void ttm_short_f32(const TIn* __restrict__ in,
   float* buf = smem + 4 * L * KG + wave * wbuf;  // this wave's area
   const int64_t a0 = ((int64_t)blockIdx.x * 4 + wave) * G;
   if (a0 >= A) return;  // whole wave idle
+  // a slab length that is a multiple of 16 puts the lanes reading one row l
+  // of their columns (or writing one output k) on at most 4 banks: such
+  // slabs sit in LDS at pitch + 1 (PAD variant).  Shorter power-of-two
+  // factors conflict less than the index division costs, so the variant
+  // without padding keeps both packed.
+  const int LB = L * B, KB = Kt * B;
+  const int P = PAD && LB % 16 == 0 ? LB + 1 : LB;
+  const int Q = PAD && KB % 16 == 0 ? KB + 1 : KB;
+  const float inv_lb = 1.0f / (float)LB, inv_kb = 1.0f / (float)KB;
   const int ga = (int)min<int64_t>(G, A - a0);
-  const int n_in = ga * L * B;  // <= 64 L
-  const TIn* src = in + a0 * L * B;
+  const int n_in = ga * LB;  // <= 64 L
+  const TIn* src = in + a0 * LB;
   float v[kShortLoads];
 #pragma unroll
   for (int u = 0; u < kShortLoads; ++u) {
@@ -1513,14 +1534,19 @@ __global__ __launch_bounds__(256) void ttm_short_f32(const TIn* __restrict__ in,
 #pragma unroll
   for (int u = 0; u < kShortLoads; ++u) {
     const int i = u * 64 + lane;
-    if (i < n_in) buf[i] = v[u];
+    if (i < n_in) {
+      if constexpr (PAD)
+        buf[i + short_div(i, LB, inv_lb) * (P - LB)] = v[u];
+      else
+        buf[i] = v[u];
+    }
   }
   wave_lds_fence();
   // lane = column c = s B + b of slab a0 + s (lanes past G B read column 0
   // and store nothing)
   const bool act = lane < ga * B;
   const int sl = act ? lane / B : 0, b = act ? lane - sl * B : 0;
-  const float* xcol = buf + sl * L * B + b;
+  const float* xcol = buf + sl * P + b;
   const float* ft = ft_all + (lane & 3) * L * KG;
   f4 acc[KG];
 #pragma unroll
@@ -1537,13 +1563,18 @@ __global__ __launch_bounds__(256) void ttm_short_f32(const TIn* __restrict__ in,
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int k = 4 * g + m;
-        if (k < Kt) buf[(sl * Kt + k) * B + b] = acc[g][m];
+        if (k < Kt) buf[sl * Q + k * B + b] = acc[g][m];
       }
   }
   wave_lds_fence();
-  const int n_out = ga * Kt * B;  // <= 64 Kt
-  float* dst = out + a0 * Kt * B;
-  for (int i = lane; i < n_out; i += 64) dst[i] = buf[i];
+  const int n_out = ga * KB;  // <= 64 Kt
+  float* dst = out + a0 * KB;
+  for (int i = lane; i < n_out; i += 64) {
+    if constexpr (PAD)
+      dst[i] = buf[i + short_div(i, KB, inv_kb) * (Q - KB)];
+    else
+      dst[i] = buf[i];
+  }
 }
 
 // Short-slab path: L <= 32, K <= 32, B = 1 or a B the row and tile bodies
@@ -1556,19 +1587,29 @@ template <typename TIn, int KG>
 hipError_t launch_short_kg(const TIn* in, int64_t A, int L, int B, const float* F, int K,
                            float* out, hipStream_t st) {
   const int G = 64 / B;
-  const int wbuf = G * B * std::max(L, K);
+  const int wbuf = G * (B * std::max(L, K) + 1);  // slabs at pitch + 1 at most
   const size_t lds = sizeof(float) * ((size_t)4 * L * KG + (size_t)4 * wbuf);
   const int64_t groups = (A + G - 1) / G;
   const int64_t blocks = (groups + 3) / 4;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   // streaming loads only where each wave's input range is whole 128-byte lines
   const bool nt = (uintptr_t)in % 128 == 0 && ((int64_t)G * L * B * sizeof(TIn)) % 128 == 0;
-  if (nt)
-    hipLaunchKernelGGL((ttm_short_f32<KG, TIn, true>), dim3((unsigned)blocks), dim3(256), lds,
-                       st, in, F, out, A, L, B, K, G, wbuf);
-  else
-    hipLaunchKernelGGL((ttm_short_f32<KG, TIn, false>), dim3((unsigned)blocks), dim3(256), lds,
-                       st, in, F, out, A, L, B, K, G, wbuf);
+  const bool pad = (L * B) % 16 == 0 || (K * B) % 16 == 0;
+#define TK_SHORT(NT_, PAD_)                                                                 \
+  hipLaunchKernelGGL((ttm_short_f32<KG, TIn, NT_, PAD_>), dim3((unsigned)blocks), dim3(256), \
+                     lds, st, in, F, out, A, L, B, K, G, wbuf)
+  if (nt) {
+    if (pad)
+      TK_SHORT(true, true);
+    else
+      TK_SHORT(true, false);
+  } else {
+    if (pad)
+      TK_SHORT(false, true);
+    else
+      TK_SHORT(false, false);
+  }
+#undef TK_SHORT
   return hipGetLastError();
 }
 
@@ -1591,8 +1632,12 @@ hipError_t launch_f32(const TIn* in, int64_t A, int L, int64_t B, const float* F
                       float* out, bool stream_in, int tile, hipStream_t st) {
   // LDS holds 16 * L * KG bytes of factor (+32 KB of tile for the tile path).
   Path path = tile == TK_TILE_STAGED ? Path::kTile : choose_path(in, out, B);
+  // short slabs: the short-slab body, except rows of 16 or more elements read
+  // 16 bytes at a time with K <= L / 2, where the row body measured faster
+  // (L = 16 and 32 with K = 4 or 8: 10-15%)
   if (tile == TK_TILE_AUTO && (path == Path::kRows || path == Path::kTile) &&
-      short_applies(L, B, K))
+      short_applies(L, B, K) &&
+      !(path == Path::kRows && rows_v4(in, L) && L >= 16 && 2 * K <= L))
     return launch_short<TIn>(in, A, L, (int)B, F, K, out, st);
   // LDS beside the factor slice: the staged tile, or the row tiles when one
   // K-group fits beside them (else 16-byte rows are read directly, and
