@@ -67,9 +67,11 @@ extern "C" {
  * AUTO   -- by shape: the wide path (B % 4 == 0, B >= 16; split over L on
  *           grids smaller than the chip; whole slabs per wave for FP32 runs
  *           that are not whole cache lines), the wide path with 4-byte loads
- *           (B >= 32 otherwise), the row path (B == 1), else the LDS-staged
- *           tile path; the K-group count from the factor's LDS footprint and
- *           the grid size;
+ *           (B >= 32 otherwise), the short-slab path (L <= 32, K <= 32 and
+ *           B = 1 or B below the wide paths: whole slabs per wave through
+ *           LDS; long aligned rows with K <= L / 2 keep the row path), the
+ *           row path (B == 1), else the LDS-staged tile path; the K-group
+ *           count from the factor's LDS footprint and the grid size;
  * STAGED -- always the LDS-staged tile path;
  * SPLITK -- AUTO's path with half the K-groups per block (more blocks, the
  *           input re-read from cache). */
