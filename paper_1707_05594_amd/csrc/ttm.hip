@@ -309,14 +309,29 @@ __device__ __forceinline__ void wide_scalar_body(const TIn* __restrict__ in,
     else
       return Elem<TIn>::to_f32(*a);
   };
+  // software-pipelined like the wide chain: U rows in flight, each row's
+  // registers refilled with the row U further on once its MFMAs are issued
   int l = 0;
-  for (; l + U <= L; l += U) {
+  if (U <= L) {
     float x[U][4];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[u][j] = ld(p[j] + (int64_t)(l + u) * B);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < 4; ++j) x[u][j] = ld(p[j] + (int64_t)u * B);
+    for (; l + 2 * U <= L; l += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int g = 0; g < KG; ++g) {
+          const float fa = ft[(l + u) * KG + g];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[u][j] = ld(p[j] + (int64_t)(l + U + u) * B);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -325,6 +340,7 @@ __device__ __forceinline__ void wide_scalar_body(const TIn* __restrict__ in,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[g][j] = mfma4x4x1(fa, x[u][j], acc[g][j]);
       }
+    l += U;
   }
   for (; l < L; ++l) {
     float x[4];
